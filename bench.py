@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput of the exponential-integrator/WENO5 march on one MI355X.
+
+One bench "step" is one pass of the whole hot path over one batch of
+synthetic input: the full inhomogeneous-medium march of an 8192 x 4096
+(tau x y) N-wave, 2000 ExpRK22 steps with x-dependent nl(x), D(x) and
+absorption, in FP32 (the FP64 multiplier tables rebuilt every step).
+Consecutive bench steps continue the march (steps k*2000 .. (k+1)*2000-1),
+so every timed step does identical work on a field resident in HBM.
+
+Prints one JSON line: value = grid-point-steps per second, plus the
+roofline of the dominant kernel (per-kernel HIP events over the timed
+region) and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+ALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}   # vector FMA without packed FP32 (256 CU x 64 lanes x 2 x 2.4 GHz)
+
+WORKLOADS = {
+    # name: (builder, default dtype)
+    "c3": "inhomogeneous medium, 8192 x 4096, 2000 steps, h = 2.5e-4, A = 1e-4",
+    "c2": "homogeneous medium, 4096 x 2048, 1000 steps, h = 5e-4",
+    "c1": "plain method, 256 x 128, 200 steps, h = 1e-3",
+}
+
+
+def kernel_model(kind, n_tau, n_y, esz):
+    """Algorithmic bytes and flops of one launch (see the design notes):
+    arrays are n_tau * n_y reals (the packed half-spectrum has the same size)."""
+    N = n_tau * n_y
+    arr = esz * N
+    lg = (n_tau.bit_length() - 1)
+    if kind == "tau_pass":
+        # read C~, write B~; two real tau-FFTs (2.5 N log2 N each) + WENO5 (~120 flops/point)
+        return 2 * arr, N * (5.0 * lg + 120.0)
+    if kind == "y_pass1":
+        # read B~, C~; write P, C~*; three complex y-FFTs of N/2 points + combine
+        lgy = (n_y.bit_length() - 1)
+        return 4 * arr, N * (3 * 2.5 * lgy + 12.0)
+    if kind == "y_pass2":
+        lgy = (n_y.bit_length() - 1)
+        return 3 * arr, N * (2 * 2.5 * lgy + 4.0)
+    return None, None
+
+
+def pmc_traffic(kernel_kind, workload, dtype):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.json" % (kernel_kind, workload, dtype))
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2103_06080_amd", "csrc", "kernels.hip"), "rb").read()
+        if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(problem):
+    """The FP64 oracle, as it stands, on one ExpRK22 step of the same grid."""
+    from oracle import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.run(problem, n_steps=1)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": problem.points / dt, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "1 ExpRK22 step of the %d x %d grid (incl. its FP64 multiplier build and the initial "
+                      "and final 2D transforms), %.1f s" % (problem.n_tau, problem.n_y, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
+              "decomposition is described in the design notes but not built" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2103_06080_amd import inputs, kzk
+
+    torch.cuda.set_device(0)
+    base = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config]()
+    steps_per_march = base.n_steps
+    total = steps_per_march * (args.warmup + args.steps)
+    prob = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config](n_steps=total)
+
+    plan = kzk.Plan(prob, dtype=args.dtype)
+    u = plan.pack([prob.u0])
+    torch.cuda.synchronize()
+
+    # warm-up marches
+    for w in range(args.warmup):
+        plan.step(u, w * steps_per_march, steps_per_march)
+    st = plan.poll()
+    if st != 0:
+        raise SystemExit("device status %d during warm-up" % st)
+
+    if not args.no_profile:
+        plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.step(u, (args.warmup + k) * steps_per_march, steps_per_march)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read() if not args.no_profile else {}
+    plan.profile(False)
+    st = plan.poll()
+    if st != 0:
+        raise SystemExit("device status %d in the timed region" % st)
+    u_host = u.double().cpu().numpy()
+    assert np.isfinite(u_host).all()
+
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    pts_steps = prob.points * steps_per_march * args.steps
+    value = pts_steps / elapsed
+    esz = 4 if args.dtype == "f32" else 8
+
+    roofline = None
+    kernels = {}
+    if prof:
+        for kind, (ms, cnt) in prof.items():
+            kernels[kind] = {"launches": cnt, "avg_us": 1e3 * ms / cnt}
+        dom = max((k for k in prof if k in ("tau_pass", "y_pass1", "y_pass2")), key=lambda k: prof[k][0])
+        avg_s = prof[dom][0] / prof[dom][1] / 1e3
+        nbytes, nflops = kernel_model(dom, prob.n_tau, prob.n_y, esz)
+        gbs = nbytes / avg_s / 1e9
+        tfl = nflops / avg_s / 1e12
+        if gbs / HBM_PEAK_GBS >= tfl / ALU_PEAK_TFLOPS[args.dtype]:
+            roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        else:
+            roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS[args.dtype],
+                        "unit": "TFLOP/s", "frac": round(tfl / ALU_PEAK_TFLOPS[args.dtype], 4)}
+        roofline["kernel"] = dom
+        roofline["avg_launch_us"] = round(avg_s * 1e6, 2)
+        roofline["algorithmic_bytes_per_launch"] = nbytes
+        roofline["algorithmic_flops_per_launch"] = nflops
+        roofline["hbm_gbs_algorithmic"] = round(gbs, 1)
+        roofline["traffic"] = pmc_traffic(dom, args.config, args.dtype)
+        # whole-step model: 11 array transfers per ExpRK22 step
+        roofline["step_model_gbs"] = round(11 * esz * prob.points * steps_per_march * args.steps / elapsed / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(base)
+
+    line = {
+        "metric": "grid-point-steps/s",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "%s: %s, %s" % (args.config, WORKLOADS[args.config], args.dtype),
+                   "n_tau": prob.n_tau, "n_y": prob.n_y, "march_steps": steps_per_march,
+                   "y_threads": plan.y_threads, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * kzk.h -- C ABI of libkzk: the time step of the exponential-integrator /
+ * WENO5 discretisation of the KZK-type sonic-boom equation (Einkemmer,
+ * Ostermann, Residori, arXiv 2103.06080), hand-written HIP for MI355X (gfx950).
+ *
+ * Equation (the paper's sigma, rho, theta, V are x, y, tau, u here):
+ *
+ *     u_x = (D/2) d_tau^{-1} d_yy u + A d_tau^2 u - nl d_tau(u^2/2)
+ *
+ * i.e. the evolution form of Sec. 3.3 eq. (14) with the linear part L of
+ * eq. (15)/(17) and the Burgers part of b (paper: D = 1/(2 pi), nl = -B).
+ * The periodic (tau, y) box of Sec. 3.4 is marched in x with step h by
+ * ExpRK22 in Fourier space (Sec. 3.3 eq. (19), Sec. 3.4 eq. (20),
+ * Algorithm 2); b is discretised with WENO5 (Jiang-Shu weights, p = 2) and
+ * Lax-Friedrichs flux splitting with speed alpha = |nl| max_tau |u| per line.
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are row-major [n_y][n_tau] (tau contiguous) device arrays of the
+ *    plan's dtype (float or double): u[j * n_tau + k] = u(tau0 + k dtau, y0 + j dy).
+ *  - The caller owns every device buffer it passes; the plan owns its
+ *    workspace.  No call frees caller memory.
+ *  - All work is enqueued on the plan's HIP stream; calls return without
+ *    synchronising, except kzk_poll.
+ *  - Errors are returned, never thrown; nothing aborts.  Argument errors are
+ *    detected before anything is enqueued.  Conditions found on the device
+ *    (CFL limit exceeded, non-finite values) are latched in a device status
+ *    word and reported by kzk_poll.
+ *  - Multiplier conventions: the mean tau-mode has l = 0 (E = 1, Phi1 = 1,
+ *    Phi2 = 1/2) and F(b)(0, .) = 0; at the tau-Nyquist index only the
+ *    absorption part of l is kept.
+ */
+#ifndef KZK_H
+#define KZK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kzk_plan kzk_plan;
+
+typedef enum {
+    KZK_OK = 0,
+    KZK_ERR_ARG = 1,       /* invalid argument (null pointer, bad size, bad dtype, ...) */
+    KZK_ERR_SIZE = 2,      /* grid size outside the supported range                      */
+    KZK_ERR_OOM = 3,       /* device allocation failed                                   */
+    KZK_ERR_DEVICE = 4,    /* a HIP call failed                                          */
+    KZK_ERR_CFL = 5,       /* device: alpha * h / dtau exceeded cfl_max on some line     */
+    KZK_ERR_NONFINITE = 6, /* device: NaN or Inf met in the field                        */
+    KZK_ERR_STATE = 7      /* step range outside the coefficient schedule, or misuse     */
+} kzk_status;
+
+typedef enum { KZK_F32 = 0, KZK_F64 = 1 } kzk_dtype;
+
+typedef struct {
+    int32_t n_tau, n_y;     /* powers of two: n_tau in [32, 8192], n_y in [16, 4096]      */
+    double tau0, L_tau;     /* periodic tau box [tau0, tau0 + L_tau)                      */
+    double y0, L_y;         /* periodic y box [y0, y0 + L_y)                              */
+    double x0, h;           /* marching origin and step: x_n = x0 + n h (paper: Delta sigma) */
+    int32_t dtype;          /* kzk_dtype: arithmetic of every kernel; the multipliers are
+                               always built in FP64 and stored in this precision           */
+    double D;               /* diffraction (D/2) d_tau^{-1} d_yy, used when D_step == NULL */
+    double A;               /* absorption A d_tau^2, A >= 0                                */
+    double nl;              /* Burgers coefficient, used when nl_node == NULL              */
+    const double *D_step;   /* optional host array [n_steps_max]: coefficient of step n,
+                               e.g. the step average (1/h) int_{x_n}^{x_n+h} D(x) dx        */
+    const double *nl_node;  /* optional host array [n_steps_max + 1]: nl(x_n); stage 1 of
+                               step n uses nl(x_n), stage 2 uses nl(x_{n+1})                */
+    int32_t n_steps_max;    /* length of the schedules (ignored when both are NULL)        */
+    int32_t lf_scope;       /* 0: LF speed per tau-line (only value supported)             */
+    double weno_eps;        /* WENO epsilon (> 0), 1e-6 in the usual reading               */
+    double cfl_max;         /* alpha h / dtau above this latches KZK_ERR_CFL (0 -> 1.0)    */
+} kzk_params;
+
+/* Create a plan for n_inst independent solves (n_inst >= 1), params[i] for
+ * solve i; uneven grids are allowed.  Allocates the workspace, builds the
+ * twiddle table and the E/Phi1/Phi2 multiplier tables (FP64 evaluation).
+ * hip_stream: a hipStream_t, or NULL for the default stream.
+ * Returns KZK_ERR_ARG / KZK_ERR_SIZE for invalid parameters, KZK_ERR_OOM
+ * when device memory runs out, KZK_ERR_DEVICE for other HIP failures. */
+kzk_status kzk_create(const kzk_params *params, int32_t n_inst, void *hip_stream, kzk_plan **out);
+
+/* Advance the packed physical field u_dev (all solves, at the offsets of
+ * kzk_inst_offset, in the plan's dtype) in place by n_steps ExpRK22 steps,
+ * steps first_step .. first_step + n_steps - 1 (Algorithm 2, Sec. 4.2).
+ * Asynchronous.  Deterministic: the same call on the same input gives the
+ * same bits.  Running steps a..b then b..c equals running a..c up to one extra
+ * tau-transform round trip of the field at b.
+ * Returns KZK_ERR_STATE if the range leaves a given coefficient schedule. */
+kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_steps);
+
+/* Discrete adjoint of kzk_step (transpose of the Jacobian of the whole
+ * march, derived from Sec. 3.3 eq. (19)): given the field u0_dev at step
+ * first_step and lam_dev = dL/du at step first_step + n_steps, write dL/du0
+ * into grad_dev (may alias lam_dev).  The forward march is recomputed from
+ * checkpoints taken every ckpt_every steps.  Asynchronous. */
+kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
+                       int32_t n_steps, int32_t ckpt_every, void *grad_dev);
+
+/* Synchronise the plan's stream and return (and clear) the device status:
+ * KZK_ERR_NONFINITE, then KZK_ERR_CFL, else KZK_OK; KZK_ERR_DEVICE if the
+ * stream reports an error. */
+kzk_status kzk_poll(kzk_plan *plan);
+
+/* Element offset of solve i in the packed field buffer; the buffer holds
+ * kzk_inst_offset(plan, n_inst) elements.  Returns (size_t)-1 for bad i. */
+size_t kzk_inst_offset(const kzk_plan *plan, int32_t i);
+
+/* Replace the HIP stream the plan enqueues on (NULL: default stream). */
+kzk_status kzk_set_stream(kzk_plan *plan, void *hip_stream);
+
+/* Enable (1) or disable (0) replay of kzk_step through a captured HIP graph.
+ * The graph for one (u_dev, first_step, n_steps) is cached and reused. */
+kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
+
+/* Select the y-pass block size (256, 512 or 1024 threads; 1024 in FP32
+ * only); rebuilds the tiled multiplier tables.  0 restores the default. */
+kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
+
+/* Current y-pass block size. */
+int32_t kzk_get_y_threads(const kzk_plan *plan);
+
+/* Kernel classes reported by kzk_profile_read. */
+enum {
+    KZK_KIND_TAU = 0,        /* tau-pass: inverse tau-FFT, WENO5 b, forward tau-FFT      */
+    KZK_KIND_Y1 = 1,         /* y-pass, stage 1 (y-FFTs, E/Phi1/Phi2 combine, inverse)    */
+    KZK_KIND_Y2 = 2,         /* y-pass, stage 2                                          */
+    KZK_KIND_TABLES = 3,     /* multiplier table build (FP64)                            */
+    KZK_KIND_TRANSFORM = 4,  /* plain tau-transforms at the ends of a march              */
+    KZK_KIND_ADJ_TAU = 5,    /* adjoint tau-pass (WENO5 Jacobian transpose)              */
+    KZK_KIND_ADJ_Y = 6,      /* adjoint y-passes                                         */
+    KZK_N_KINDS = 8
+};
+
+/* Bracket every later kernel launch of the plan with HIP events on its
+ * stream (on = 1) or stop doing so (on = 0).  While on, graph replay is not
+ * used.  For measurement; adds an event record per launch. */
+kzk_status kzk_profile_enable(kzk_plan *plan, int32_t on);
+
+/* Synchronise the stream and return, per kernel class k < n_kinds, the summed
+ * event time ms[k] (milliseconds) and the number of launches count[k] since
+ * the last read; then forget them. */
+kzk_status kzk_profile_read(kzk_plan *plan, double *ms, int32_t *count, int32_t n_kinds);
+
+/* Release the plan and its device memory (after finishing its stream work). */
+void kzk_destroy(kzk_plan *plan);
+
+const char *kzk_status_str(kzk_status s);
+
+/* ---- single-operator entry points (used for per-kernel parity) ----
+ * Each applies one piece of the step to every solve of the plan. */
+
+/* b = -nl d_tau(u^2/2) by WENO5/LF on every tau-line of u_dev, with
+ * nl = nl(x_node) (Sec. 3.4): b_dev receives the physical field b.  Runs the
+ * production tau-pass kernel between a forward and an inverse tau-transform. */
+kzk_status kzk_eval_b(kzk_plan *plan, const void *u_dev, int32_t node, void *b_dev);
+
+/* Forward tau-transform of the physical field (R2C along tau, packed: slot 0
+ * holds (X_0, X_{n_tau/2})) into spec_dev, M = n_tau/2 complex per row. */
+kzk_status kzk_tau_forward(kzk_plan *plan, const void *u_dev, void *spec_dev);
+
+/* Inverse of kzk_tau_forward (scaled by 1/n_tau). */
+kzk_status kzk_tau_inverse(kzk_plan *plan, const void *spec_dev, void *u_dev);
+
+/* Copy the multiplier tables of solve inst into out_dev (device buffer of
+ * 3 * (n_tau/2) * (n_y/2 + 1) complex values of the plan's dtype), ordered
+ * [table][m][n] for tau-mode m < n_tau/2 and |ky index| n <= n_y/2, tables
+ * E/n_y, h Phi1/n_y, h Phi2/n_y of z = h l(m, n) (Sec. 3.4); entry (m = 0,
+ * n = 0) holds the unscaled tau-Nyquist scalars e^z, h phi1(z), h phi2(z)
+ * with z = -h A k_N^2, other m = 0 entries are zero.  Synchronises. */
+kzk_status kzk_read_tables(kzk_plan *plan, int32_t inst, void *out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

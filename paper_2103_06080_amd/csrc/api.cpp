@@ -1,0 +1,525 @@
+// api.cpp -- host runtime and C ABI of libkzk (plan, workspace, launches).
+#include "../../include/kzk.h"
+#include "internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using kzk::InstDesc;
+using kzk::TauItem;
+using kzk::YItem;
+
+namespace {
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2i(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct kzk_plan {
+    int n_inst = 0;
+    int dtype = KZK_F64;
+    size_t esz = 8;                       // bytes per real
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<kzk_params> params;
+    std::vector<std::vector<double>> Dsched, nlsched;
+    std::vector<InstDesc> desc;
+    std::vector<size_t> u_off;            // n_inst + 1 real offsets
+    size_t state_elems = 0, tab_elems = 0;
+    int ntw = 0, log2_ntw = 0;
+    int y_threads = 0;
+    bool any_D_sched = false;
+    long long steps_limit = -1;           // -1: unlimited (constant coefficients)
+
+    void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dTab = nullptr, *dTw = nullptr;
+    InstDesc* dDesc = nullptr;
+    TauItem* dTau = nullptr;
+    YItem* dY = nullptr;
+    int n_tau_items = 0, n_y_items = 0;
+    unsigned* dStatus = nullptr;
+    double* dSched = nullptr;
+    std::vector<void*> owned;             // everything hipMalloc'ed, freed in destroy
+
+    bool graph_on = false;
+    hipGraphExec_t gexec = nullptr;
+    const void* g_u = nullptr;
+    int g_first = -1, g_n = -1;
+
+    // per-kernel timing with HIP events (kzk_profile_enable)
+    bool prof = false;
+    struct Ev { int kind; hipEvent_t a, b; };
+    std::vector<Ev> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+
+    // adjoint workspace (allocated on first use)
+    void *dL = nullptr, *dMu = nullptr, *dCk = nullptr, *dUn = nullptr, *dUs = nullptr, *dT = nullptr;
+    size_t adj_ckpt_cap = 0, adj_seg_cap = 0;
+};
+
+namespace {
+
+kzk_status dev_alloc(kzk_plan* p, void** out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return KZK_ERR_OOM;
+    }
+    p->owned.push_back(*out);
+    return KZK_OK;
+}
+
+void drop_graph(kzk_plan* p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->g_u = nullptr;
+    p->g_first = p->g_n = -1;
+}
+
+hipEvent_t take_event(kzk_plan* p) {
+    if (!p->ev_pool.empty()) {
+        hipEvent_t e = p->ev_pool.back();
+        p->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    kzk_plan* p;
+    int kind;
+    hipEvent_t a = nullptr;
+    ProfScope(kzk_plan* p_, int kind_) : p(p_), kind(kind_) {
+        if (p->prof && (a = take_event(p))) (void)hipEventRecord(a, p->stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = take_event(p);
+        if (!b) { p->ev_pool.push_back(a); return; }
+        (void)hipEventRecord(b, p->stream);
+        p->ev_used.push_back({kind, a, b});
+    }
+};
+
+kzk_status check_params(const kzk_params& q) {
+    if (!pow2(q.n_tau) || !pow2(q.n_y)) return KZK_ERR_SIZE;
+    if (q.n_tau < 32 || q.n_tau > 8192 || q.n_y < 16 || q.n_y > 4096) return KZK_ERR_SIZE;
+    if (!(q.L_tau > 0) || !(q.L_y > 0) || !(q.h > 0) || !std::isfinite(q.h)) return KZK_ERR_ARG;
+    if (q.dtype != KZK_F32 && q.dtype != KZK_F64) return KZK_ERR_ARG;
+    if (!(q.A >= 0) || !std::isfinite(q.A) || !std::isfinite(q.D) || !std::isfinite(q.nl)) return KZK_ERR_ARG;
+    if (!(q.weno_eps > 0)) return KZK_ERR_ARG;
+    if (q.lf_scope != 0) return KZK_ERR_ARG;
+    if (q.cfl_max < 0) return KZK_ERR_ARG;
+    if ((q.D_step || q.nl_node) && q.n_steps_max < 0) return KZK_ERR_ARG;
+    return KZK_OK;
+}
+
+int default_y_threads(int dtype) { return dtype == KZK_F32 ? 1024 : 512; }
+
+// Descriptors, work lists and tables for the current y-pass block size.
+kzk_status layout(kzk_plan* p) {
+    std::vector<TauItem> tau;
+    std::vector<YItem> ys;
+    for (int i = 0; i < p->n_inst; ++i) {
+        InstDesc& d = p->desc[i];
+        int W = std::min(p->y_threads * 16 / d.n_y, d.M);
+        d.W = W;
+        d.log2W = ilog2i(W);
+        for (int r = 0; r < d.n_y; r += d.rows_per_tau_block) tau.push_back({i, r});
+        for (int m = 0; m < d.M; m += W) ys.push_back({i, m});
+    }
+    // the item arrays are sized for the largest case at create (W >= 1)
+    if ((int)tau.size() > p->n_tau_items && p->dTau) return KZK_ERR_STATE;
+    p->n_tau_items = (int)tau.size();
+    p->n_y_items = (int)ys.size();
+    if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->dTau, tau.data(), sizeof(TauItem) * tau.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->dY, ys.data(), sizeof(YItem) * ys.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+
+kzk_status build_tables(kzk_plan* p, int step, bool only_scheduled) {
+    for (int i = 0; i < p->n_inst; ++i) {
+        bool sched = p->desc[i].D_step != nullptr;
+        if (only_scheduled && !sched) continue;
+        int st = sched ? std::min<long long>(step, std::max<long long>(0, (long long)p->Dsched[i].size() - 1)) : 0;
+        ProfScope ps(p, KZK_KIND_TABLES);
+        hipError_t e = p->dtype == KZK_F32
+            ? kzk::launch_tables<float>(p->dDesc, i, (int)p->desc[i].tab_size, p->dTab, st, p->stream)
+            : kzk::launch_tables<double>(p->dDesc, i, (int)p->desc[i].tab_size, p->dTab, st, p->stream);
+        if (e != hipSuccess) return KZK_ERR_DEVICE;
+    }
+    return KZK_OK;
+}
+
+hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void* Cin, void* Bout, int node) {
+    ProfScope ps(p, mode == 2 ? KZK_KIND_TAU : KZK_KIND_TRANSFORM);
+    if (p->dtype == KZK_F32)
+        return kzk::launch_tau<float>(mode, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in, (float*)u_out,
+                                      Cin, Bout, p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+    return kzk::launch_tau<double>(mode, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in, (double*)u_out,
+                                   Cin, Bout, p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+}
+
+hipError_t ypass(kzk_plan* p, int stage) {
+    ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : KZK_KIND_Y2);
+    if (p->dtype == KZK_F32)
+        return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP,
+                                    p->dTab, p->dTw, p->log2_ntw, p->stream);
+    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP, p->dTab,
+                                 p->dTw, p->log2_ntw, p->stream);
+}
+
+// Steps s .. s+n-1 on the spectral state dC (no transforms at the ends).
+kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
+    for (int s = first; s < first + n; ++s) {
+        if (p->any_D_sched) {
+            kzk_status st = build_tables(p, s, true);
+            if (st != KZK_OK) return st;
+        }
+        if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if (ypass(p, 1) != hipSuccess) return KZK_ERR_DEVICE;
+        if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s + 1) != hipSuccess) return KZK_ERR_DEVICE;
+        if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
+    }
+    return KZK_OK;
+}
+
+kzk_status enqueue_march(kzk_plan* p, void* u, int first, int n) {
+    if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    kzk_status st = enqueue_steps(p, first, n);
+    if (st != KZK_OK) return st;
+    if (tau(p, 1, nullptr, u, p->dC, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+
+kzk_status check_range(const kzk_plan* p, long long first, long long n) {
+    if (first < 0 || n < 0) return KZK_ERR_ARG;
+    if (p->steps_limit >= 0 && first + n > p->steps_limit) return KZK_ERR_STATE;
+    return KZK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kzk_status_str(kzk_status s) {
+    switch (s) {
+    case KZK_OK: return "ok";
+    case KZK_ERR_ARG: return "invalid argument";
+    case KZK_ERR_SIZE: return "grid size not supported";
+    case KZK_ERR_OOM: return "out of device memory";
+    case KZK_ERR_DEVICE: return "HIP error";
+    case KZK_ERR_CFL: return "CFL limit exceeded";
+    case KZK_ERR_NONFINITE: return "non-finite value in the field";
+    case KZK_ERR_STATE: return "invalid state or step range";
+    }
+    return "unknown status";
+}
+
+void kzk_destroy(kzk_plan* p) {
+    if (!p) return;
+    drop_graph(p);
+    for (auto& e : p->ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto e : p->ev_pool) (void)hipEventDestroy(e);
+    for (void* q : p->owned) (void)hipFree(q);
+    delete p;
+}
+
+kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream, kzk_plan** out) {
+    if (!out) return KZK_ERR_ARG;
+    *out = nullptr;
+    if (!params || n_inst < 1) return KZK_ERR_ARG;
+    for (int i = 0; i < n_inst; ++i) {
+        kzk_status st = check_params(params[i]);
+        if (st != KZK_OK) return st;
+        if (params[i].dtype != params[0].dtype) return KZK_ERR_ARG;
+    }
+    kzk_plan* p = new (std::nothrow) kzk_plan();
+    if (!p) return KZK_ERR_OOM;
+    p->n_inst = n_inst;
+    p->dtype = params[0].dtype;
+    p->esz = p->dtype == KZK_F32 ? 4 : 8;
+    p->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&p->device);
+    p->params.assign(params, params + n_inst);
+    p->Dsched.resize(n_inst);
+    p->nlsched.resize(n_inst);
+    p->desc.resize(n_inst);
+    p->u_off.resize(n_inst + 1);
+    p->y_threads = default_y_threads(p->dtype);
+
+    size_t so = 0, uo = 0, to = 0, nsched = 0;
+    int ntw = 0, max_tau_items = 0, max_y_items = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const kzk_params& q = params[i];
+        InstDesc& d = p->desc[i];
+        std::memset(&d, 0, sizeof(d));
+        d.n_tau = q.n_tau;
+        d.n_y = q.n_y;
+        d.M = q.n_tau / 2;
+        d.Nh = q.n_y / 2 + 1;
+        d.rows_per_tau_block = kzk::TAU_THREADS * 16 / d.M;
+        d.off_state = (long long)so;
+        d.off_u = (long long)uo;
+        d.off_tab = (long long)to;
+        d.tab_size = (long long)d.M * d.Nh;
+        d.dtau = q.L_tau / q.n_tau;
+        d.h = q.h;
+        d.L_tau = q.L_tau;
+        d.L_y = q.L_y;
+        d.A = q.A;
+        d.weno_eps = q.weno_eps;
+        d.D_const = q.D;
+        d.nl_const = q.nl;
+        d.cfl_max = q.cfl_max > 0 ? q.cfl_max : 1.0;
+        p->u_off[i] = uo;
+        so += (size_t)d.M * q.n_y;
+        uo += (size_t)q.n_tau * q.n_y;
+        to += (size_t)d.M * d.Nh;
+        ntw = std::max(ntw, std::max(q.n_tau, q.n_y));
+        max_tau_items += (q.n_y + d.rows_per_tau_block - 1) / d.rows_per_tau_block;
+        max_y_items += d.M;   // W >= 1
+        if (q.D_step) {
+            p->Dsched[i].assign(q.D_step, q.D_step + q.n_steps_max);
+            p->any_D_sched = true;
+        }
+        if (q.nl_node) p->nlsched[i].assign(q.nl_node, q.nl_node + q.n_steps_max + 1);
+        if (q.D_step || q.nl_node) {
+            long long lim = q.n_steps_max;
+            p->steps_limit = p->steps_limit < 0 ? lim : std::min(p->steps_limit, lim);
+        }
+        nsched += p->Dsched[i].size() + p->nlsched[i].size();
+    }
+    p->u_off[n_inst] = uo;
+    p->state_elems = so;
+    p->tab_elems = to;
+    for (int i = 0; i < n_inst; ++i) p->desc[i].tab_stride = (long long)to;
+    p->ntw = ntw;
+    p->log2_ntw = ilog2i(ntw);
+
+    const size_t cz = 2 * p->esz;   // bytes per complex
+    kzk_status st = KZK_OK;
+    if ((st = dev_alloc(p, &p->dC, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dB, so * cz)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dP, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dTab, 3 * to * cz)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dTw, (size_t)ntw * cz)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dDesc, sizeof(InstDesc) * n_inst)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dTau, sizeof(TauItem) * max_tau_items)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dY, sizeof(YItem) * max_y_items)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dStatus, 256)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dSched, sizeof(double) * (nsched + 1))) != KZK_OK) {
+        kzk_destroy(p);
+        return st;
+    }
+    p->n_tau_items = max_tau_items;
+
+    // coefficient schedules
+    {
+        std::vector<double> all;
+        all.reserve(nsched);
+        std::vector<size_t> offD(n_inst), offN(n_inst);
+        for (int i = 0; i < n_inst; ++i) {
+            offD[i] = all.size();
+            all.insert(all.end(), p->Dsched[i].begin(), p->Dsched[i].end());
+            offN[i] = all.size();
+            all.insert(all.end(), p->nlsched[i].begin(), p->nlsched[i].end());
+        }
+        if (!all.empty() &&
+            hipMemcpy(p->dSched, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            kzk_destroy(p);
+            return KZK_ERR_DEVICE;
+        }
+        for (int i = 0; i < n_inst; ++i) {
+            p->desc[i].D_step = p->Dsched[i].empty() ? nullptr : p->dSched + offD[i];
+            p->desc[i].nl_node = p->nlsched[i].empty() ? nullptr : p->dSched + offN[i];
+        }
+    }
+    // twiddles exp(-2 pi i k / ntw) in FP64, stored in the working precision
+    {
+        std::vector<double> tw(2 * (size_t)ntw);
+        for (int k = 0; k < ntw; ++k) {
+            double a = 2.0 * M_PI * (double)k / (double)ntw;
+            tw[2 * k] = std::cos(a);
+            tw[2 * k + 1] = -std::sin(a);
+        }
+        hipError_t e;
+        if (p->dtype == KZK_F32) {
+            std::vector<float> f(tw.begin(), tw.end());
+            e = hipMemcpy(p->dTw, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(p->dTw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+    }
+    if (hipMemset(p->dStatus, 0, 256) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+    if ((st = layout(p)) != KZK_OK || (st = build_tables(p, 0, false)) != KZK_OK) {
+        kzk_destroy(p);
+        return st;
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+    *out = p;
+    return KZK_OK;
+}
+
+kzk_status kzk_set_stream(kzk_plan* p, void* s) {
+    if (!p) return KZK_ERR_ARG;
+    p->stream = (hipStream_t)s;
+    return KZK_OK;
+}
+
+kzk_status kzk_set_graph(kzk_plan* p, int32_t enable) {
+    if (!p) return KZK_ERR_ARG;
+    p->graph_on = enable != 0;
+    if (!p->graph_on) drop_graph(p);
+    return KZK_OK;
+}
+
+int32_t kzk_get_y_threads(const kzk_plan* p) { return p ? p->y_threads : 0; }
+
+kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
+    if (!p) return KZK_ERR_ARG;
+    if (threads == 0) threads = default_y_threads(p->dtype);
+    if (!kzk::y_threads_supported(p->dtype == KZK_F64, threads)) return KZK_ERR_ARG;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    drop_graph(p);
+    p->y_threads = threads;
+    kzk_status st = layout(p);
+    if (st != KZK_OK) return st;
+    st = build_tables(p, 0, false);
+    if (st != KZK_OK) return st;
+    return hipStreamSynchronize(p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
+
+size_t kzk_inst_offset(const kzk_plan* p, int32_t i) {
+    if (!p || i < 0 || i > p->n_inst) return (size_t)-1;
+    return p->u_off[i];
+}
+
+kzk_status kzk_step(kzk_plan* p, void* u, int32_t first, int32_t n) {
+    if (!p || !u) return KZK_ERR_ARG;
+    kzk_status st = check_range(p, first, n);
+    if (st != KZK_OK) return st;
+    if (n == 0) return KZK_OK;
+    if (!p->graph_on || p->prof) return enqueue_march(p, u, first, n);
+    if (!p->stream) return KZK_ERR_STATE;   // the legacy default stream cannot be captured
+    if (!(p->gexec && p->g_u == u && p->g_first == first && p->g_n == n)) {
+        drop_graph(p);
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return KZK_ERR_DEVICE;
+        kzk_status cs = enqueue_march(p, u, first, n);
+        hipError_t e = hipStreamEndCapture(p->stream, &g);
+        if (cs != KZK_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return cs != KZK_OK ? cs : KZK_ERR_DEVICE;
+        }
+        e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { p->gexec = nullptr; return KZK_ERR_DEVICE; }
+        p->g_u = u;
+        p->g_first = first;
+        p->g_n = n;
+    }
+    return hipGraphLaunch(p->gexec, p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
+
+kzk_status kzk_profile_enable(kzk_plan* p, int32_t on) {
+    if (!p) return KZK_ERR_ARG;
+    p->prof = on != 0;
+    return KZK_OK;
+}
+
+kzk_status kzk_profile_read(kzk_plan* p, double* ms, int32_t* count, int32_t n_kinds) {
+    if (!p || !ms || !count || n_kinds < 0) return KZK_ERR_ARG;
+    for (int k = 0; k < n_kinds; ++k) { ms[k] = 0; count[k] = 0; }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    kzk_status st = KZK_OK;
+    for (auto& e : p->ev_used) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) st = KZK_ERR_DEVICE;
+        if (e.kind < n_kinds) { ms[e.kind] += t; count[e.kind] += 1; }
+        p->ev_pool.push_back(e.a);
+        p->ev_pool.push_back(e.b);
+    }
+    p->ev_used.clear();
+    return st;
+}
+
+kzk_status kzk_poll(kzk_plan* p) {
+    if (!p) return KZK_ERR_ARG;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    unsigned s = 0;
+    if (hipMemcpy(&s, p->dStatus, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess) return KZK_ERR_DEVICE;
+    if (s) {
+        if (hipMemset(p->dStatus, 0, sizeof(unsigned)) != hipSuccess) return KZK_ERR_DEVICE;
+        if (hipDeviceSynchronize() != hipSuccess) return KZK_ERR_DEVICE;
+    }
+    if (s & kzk::ST_NONFINITE) return KZK_ERR_NONFINITE;
+    if (s & kzk::ST_CFL) return KZK_ERR_CFL;
+    return KZK_OK;
+}
+
+kzk_status kzk_eval_b(kzk_plan* p, const void* u, int32_t node, void* b) {
+    if (!p || !u || !b) return KZK_ERR_ARG;
+    if (node < 0 || (p->steps_limit >= 0 && node > p->steps_limit)) return KZK_ERR_STATE;
+    if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, node) != hipSuccess) return KZK_ERR_DEVICE;
+    if (tau(p, 1, nullptr, b, p->dB, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+
+kzk_status kzk_tau_forward(kzk_plan* p, const void* u, void* spec) {
+    if (!p || !u || !spec) return KZK_ERR_ARG;
+    return tau(p, 0, u, nullptr, nullptr, spec, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
+
+kzk_status kzk_tau_inverse(kzk_plan* p, const void* spec, void* u) {
+    if (!p || !u || !spec) return KZK_ERR_ARG;
+    return tau(p, 1, nullptr, u, spec, nullptr, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
+
+kzk_status kzk_read_tables(kzk_plan* p, int32_t inst, void* out) {
+    if (!p || !out || inst < 0 || inst >= p->n_inst) return KZK_ERR_ARG;
+    const InstDesc& d = p->desc[inst];
+    const size_t cz = 2 * p->esz, n = (size_t)d.tab_size;
+    std::vector<char> tile(3 * n * cz), lin(3 * n * cz);
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    for (int t = 0; t < 3; ++t)
+        if (hipMemcpy(tile.data() + t * n * cz, (char*)p->dTab + ((size_t)t * d.tab_stride + d.off_tab) * cz, n * cz,
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return KZK_ERR_DEVICE;
+    for (int t = 0; t < 3; ++t)
+        for (int m = 0; m < d.M; ++m)
+            for (int q = 0; q < d.Nh; ++q) {
+                const int c = m & (d.W - 1);
+                const size_t src = (size_t)(m - c) * d.Nh + (size_t)q * d.W + c;
+                const size_t dst = (size_t)m * d.Nh + q;
+                std::memcpy(lin.data() + (t * n + dst) * cz, tile.data() + (t * n + src) * cz, cz);
+            }
+    return hipMemcpy(out, lin.data(), lin.size(), hipMemcpyHostToDevice) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
+
+kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n, int32_t ckpt,
+                       void* grad) {
+    (void)u0; (void)lam; (void)first; (void)n; (void)ckpt; (void)grad;
+    if (!p) return KZK_ERR_ARG;
+    return KZK_ERR_STATE;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// internal.hpp -- data shared by the host runtime and the kernels of libkzk.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace kzk {
+
+// Status bits latched by the kernels (vector atomics on a device word).
+enum : unsigned { ST_CFL = 1u, ST_NONFINITE = 2u };
+
+// Threads of a tau-pass block.  A tau-line of n_tau reals is handled as a
+// complex sequence of M = n_tau/2 points by M/16 threads; a block holds
+// 256*16 = 4096 complex points, i.e. 8192/n_tau lines.
+constexpr int TAU_THREADS = 256;
+
+// One solve of a (possibly batched) plan, as the kernels see it.
+struct InstDesc {
+    int n_tau, n_y;        // grid points along tau and y
+    int M, Nh;             // M = n_tau/2 complex tau-modes (packed), Nh = n_y/2 + 1
+    int W, log2W;          // y-pass tile width (columns per block)
+    int rows_per_tau_block;
+    int pad0;
+    long long off_state;   // complex offset of this solve in the C, B, P arrays
+    long long off_u;       // real offset of this solve in the packed physical field
+    long long off_tab;     // complex offset in each multiplier table
+    long long tab_size;    // M * Nh elements of this solve in each table
+    long long tab_stride;  // distance between the E, Phi1 and Phi2 tables (all solves)
+    double dtau, h, L_tau, L_y, A, weno_eps;
+    double D_const, nl_const, cfl_max;
+    const double* nl_node;   // device [n_steps_max+1] or nullptr -> nl_const
+    const double* D_step;    // device [n_steps_max]   or nullptr -> D_const
+};
+
+struct TauItem { int inst, row0; };
+struct YItem { int inst, m0; };
+
+// Launchers (kernels.hip).  All enqueue on `s` and return hipSuccess or the
+// launch error.
+template <typename T>
+hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items,
+                      const T* u_in, T* u_out, const void* Cin, void* Bout, const void* tw,
+                      int log2_ntw, int node, unsigned* status, hipStream_t s);
+
+template <typename T>
+hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                    void* C, const void* B, void* P, const void* tabs, const void* tw, int log2_ntw,
+                    hipStream_t s);
+
+template <typename T>
+hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step,
+                         hipStream_t s);
+
+// Block sizes of the y-pass for which kernels are compiled.
+bool y_threads_supported(int dtype_is_f64, int nt);
+
+}  // namespace kzk

@@ -1,0 +1,543 @@
+// kernels.hip -- HIP kernels of the exponential-integrator/WENO5 step (gfx950).
+//
+// State between steps: C~(m, y), the tau-spectrum of u for every y-row
+// (y physical), packed R2C layout: M = n_tau/2 complex per row, slot 0 holds
+// the real DC mode in .x and the real tau-Nyquist mode in .y.
+//
+// One ExpRK22 step (Sec. 3.4 eq. (20), Algorithm 2) is four kernels:
+//   tau-pass (node x_n)      C~  -> inverse tau-FFT -> u^n -> LF speed ->
+//                                    WENO5 b -> forward tau-FFT -> B~
+//   y-pass stage 1           y-FFT of B~ and C~, E/Phi1/Phi2 combine:
+//                                    U* = E U + h Phi1 B,  P = E U + h (Phi1-Phi2) B,
+//                                    inverse y-FFT of U* -> C~ (in place), P kept
+//   tau-pass (node x_{n+1})  C~* -> B~*
+//   y-pass stage 2           U^{n+1} = P + h Phi2 B*, inverse y-FFT -> C~
+// Column 0 (DC and tau-Nyquist) needs no y-FFT: the DC multipliers are
+// (1, 1, 1/2) with F(b)(0, .) = 0, so the DC column is left untouched, and
+// the Nyquist multipliers do not depend on ky, so they act pointwise in y.
+#include "fft.hpp"
+#include "internal.hpp"
+
+#include <float.h>
+
+namespace kzk {
+
+constexpr double KZK_PI = 3.14159265358979323846264338327950288;
+
+template <typename T> struct alignas(4 * sizeof(T)) quad { T v[4]; };
+
+template <typename T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) {
+    // hardware estimate refined by two Newton steps
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ bool finite_val(T x);
+template <> __device__ __forceinline__ bool finite_val<float>(float x) { return fabsf(x) <= FLT_MAX; }
+template <> __device__ __forceinline__ bool finite_val<double>(double x) { return fabs(x) <= DBL_MAX; }
+
+// ------------------------------------------------------------------ WENO5-JS
+// Face value from the upwind-ordered stencil v0..v4 (v2 on the upwind side of
+// the face): candidates q_r, smoothness indicators beta_r (Jiang-Shu), ideal
+// weights (1/10, 6/10, 3/10), p = 2.  The three nonlinear weights share one
+// reciprocal: w_r ~ d_r prod_{s != r} (eps + beta_s)^2.
+template <typename T>
+__device__ __forceinline__ T weno_face(T v0, T v1, T v2, T v3, T v4, T eps) {
+    const T c1312 = (T)(13.0 / 12.0);
+    T q0 = (T)2 * v0 - (T)7 * v1 + (T)11 * v2;
+    T q1 = -v1 + (T)5 * v2 + (T)2 * v3;
+    T q2 = (T)2 * v2 + (T)5 * v3 - v4;
+    T a0 = v0 - (T)2 * v1 + v2, b0 = v0 - (T)4 * v1 + (T)3 * v2;
+    T a1 = v1 - (T)2 * v2 + v3, b1 = v1 - v3;
+    T a2 = v2 - (T)2 * v3 + v4, b2 = (T)3 * v2 - (T)4 * v3 + v4;
+    T s0 = eps + c1312 * a0 * a0 + (T)0.25 * b0 * b0;
+    T s1 = eps + c1312 * a1 * a1 + (T)0.25 * b1 * b1;
+    T s2 = eps + c1312 * a2 * a2 + (T)0.25 * b2 * b2;
+    s0 *= s0; s1 *= s1; s2 *= s2;
+    T w0 = (T)0.1 * s1 * s2, w1 = (T)0.6 * s0 * s2, w2 = (T)0.3 * s0 * s1;
+    return (w0 * q0 + w1 * q1 + w2 * q2) * rcp((T)6 * (w0 + w1 + w2));
+}
+
+// ------------------------------------------------------------------ block helpers
+
+// Max over the tpr threads of one line (lines are aligned groups of tpr
+// consecutive threads; tpr is a power of two).  red: 4 LDS slots.
+template <typename T>
+__device__ __forceinline__ T line_max(T v, int tpr, T* red) {
+    const int w = tpr < 64 ? tpr : 64;
+    for (int o = w >> 1; o > 0; o >>= 1) v = tmax(v, __shfl_xor(v, o));
+    if (tpr > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = v;
+        __syncthreads();
+        const int nw = tpr >> 6, first = (threadIdx.x / tpr) * nw;
+        T m = red[first];
+        for (int i = 1; i < nw; ++i) m = tmax(m, red[first + i]);
+        v = m;
+        __syncthreads();
+    }
+    return v;
+}
+
+__device__ __forceinline__ int line_or(int v, int tpr, int* red) {
+    const int w = tpr < 64 ? tpr : 64;
+    for (int o = w >> 1; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    if (tpr > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = v;
+        __syncthreads();
+        const int nw = tpr >> 6, first = (threadIdx.x / tpr) * nw;
+        int m = 0;
+        for (int i = 0; i < nw; ++i) m |= red[first + i];
+        v = m;
+        __syncthreads();
+    }
+    return v;
+}
+
+// Block index -> work item so that items with consecutive indices run on the
+// same XCD (blocks are dispatched round-robin over the 8 XCDs): neighbouring
+// column tiles share cache lines of the row-major spectra.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// ------------------------------------------------------------------ tau-pass
+// Real <-> packed half-spectrum along tau, using one complex FFT of M = N/2
+// points: z_j = u_{2j} + i u_{2j+1}.
+//
+// Inverse (C2R), for the pair k, M-k (k = 0..M/2), scaled by 1/N:
+//   A = X_k + conj X_{M-k},  P = i e^{+2 pi i k/N} (X_k - conj X_{M-k}),
+//   Z_k = A + P,  Z_{M-k} = conj(A - P)
+// Forward (R2C) from Z = FFT(z):
+//   A = (Z_k + conj Z_{M-k})/2,  Q = i e^{-2 pi i k/N} (Z_k - conj Z_{M-k})/2,
+//   X_k = A - Q,  X_{M-k} = conj(A + Q),  slot 0 = (X_0, X_M).
+
+template <typename T>
+__device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, cpx<T>* lds, int base, int M, int t, int tpr,
+                                        const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
+    const int lg_n = ilog2(2 * M);
+    for (int k = t; k <= (M >> 1); k += tpr) {
+        if (k == 0) {
+            cpx<T> s = X[0];
+            lds[base] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
+            continue;
+        }
+        cpx<T> xk = X[k], xm = X[M - k];
+        cpx<T> A = {xk.x + xm.x, xk.y - xm.y};
+        cpx<T> D = {xk.x - xm.x, xk.y + xm.y};
+        cpx<T> w = conj(tw[k << (log2_ntw - lg_n)]);      // e^{+2 pi i k/N}
+        cpx<T> P = mul_si<1>(cmul(w, D));
+        cpx<T> zk = A + P;
+        lds[base + k] = inv_n * zk;
+        if (2 * k != M) {
+            cpx<T> zm = conj(A - P);
+            lds[base + M - k] = inv_n * zm;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, int M, int t, int tpr,
+                                         const cpx<T>* __restrict__ tw, int log2_ntw) {
+    const int lg_n = ilog2(2 * M);
+    for (int k = t; k <= (M >> 1); k += tpr) {
+        cpx<T> zk = lds[base + k];
+        cpx<T> zm = lds[base + ((M - k) & (M - 1))];
+        cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+        cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
+        cpx<T> w = tw[k << (log2_ntw - lg_n)];             // e^{-2 pi i k/N}
+        cpx<T> Q = mul_si<1>(cmul(w, D));
+        if (k == 0) {
+            X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
+            continue;
+        }
+        X[k] = A - Q;
+        if (2 * k != M) X[M - k] = conj(A + Q);
+    }
+}
+
+// MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B (b via WENO5).
+template <typename T, int MODE>
+__global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __restrict__ descs,
+                                                          const TauItem* __restrict__ items,
+                                                          const T* __restrict__ u_in, T* __restrict__ u_out,
+                                                          const cpx<T>* __restrict__ Cin, cpx<T>* __restrict__ Bout,
+                                                          const cpx<T>* __restrict__ tw, int log2_ntw, int node,
+                                                          unsigned* __restrict__ status) {
+    __shared__ alignas(32) cpx<T> lds[TAU_THREADS * 16];
+    __shared__ T redT[4];
+    __shared__ int redI[4];
+    const TauItem it = items[blockIdx.x];
+    const InstDesc& d = descs[it.inst];
+    const int M = d.M, N = 2 * M;
+    const int tpr = M >> 4;
+    const int r = threadIdx.x / tpr, t = threadIdx.x & (tpr - 1);
+    const int row = it.row0 + r;
+    const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
+    const int base = r * M;
+    const int Nc = M >> 1;   // chunks of 4 reals per line
+    quad<T>* q4 = reinterpret_cast<quad<T>*>(lds + base);
+    const long long so = d.off_state + (long long)row * M;
+
+    if (MODE == 0) {
+        const quad<T>* ug = reinterpret_cast<const quad<T>*>(u_in + d.off_u + (long long)row * N);
+        int bad = 0;
+        if (active)
+            for (int c = t; c < Nc; c += tpr) {
+                quad<T> v = ug[c];
+                bad |= !(finite_val(v.v[0]) && finite_val(v.v[1]) && finite_val(v.v[2]) && finite_val(v.v[3]));
+                q4[c] = v;
+            }
+        bad = line_or(bad, tpr, redI);
+        if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
+        __syncthreads();
+        lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
+        if (active) r2c_post(lds, base, Bout + so, M, t, tpr, tw, log2_ntw);
+        return;
+    }
+
+    // inverse tau-transform of C~ into the line buffer
+    if (active) c2r_pre(Cin + so, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    __syncthreads();
+    lds_fft<T, 1>(lds, base, 1, M, t, active, tw, log2_ntw);
+
+    if (MODE == 1) {
+        quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
+        if (active)
+            for (int c = t; c < Nc; c += tpr) ug[c] = q4[c];
+        return;
+    }
+
+    // ---- LF speed alpha = |nl(x_node)| max|u| over the line (exact in any precision)
+    T mx = 0;
+    int bad = 0;
+    if (active)
+        for (int c = t; c < Nc; c += tpr) {
+            quad<T> v = q4[c];
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bad |= !finite_val(v.v[i]);
+                mx = tmax(mx, (T)fabs(v.v[i]));
+            }
+        }
+    mx = line_max(mx, tpr, redT);
+    bad = line_or(bad, tpr, redI);
+    const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
+    const T nlT = (T)nl;
+    const T alpha = (T)fabs(nl) * mx;
+    if (active && t == 0) {
+        unsigned f = 0;
+        if (bad) f |= ST_NONFINITE;
+        if ((double)alpha * d.h > d.cfl_max * d.dtau) f |= ST_CFL;
+        if (f) atomicOr(status, f);
+    }
+
+    // ---- WENO5 fluxes at the faces 4c + k + 1/2 of my chunks
+    const T eps = (T)d.weno_eps;
+    T F[8][4];
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active && c < Nc) {
+            quad<T> a = q4[(c - 1) & (Nc - 1)], b = q4[c], e = q4[(c + 1) & (Nc - 1)];
+            T u[12] = {a.v[0], a.v[1], a.v[2], a.v[3], b.v[0], b.v[1], b.v[2], b.v[3],
+                       e.v[0], e.v[1], e.v[2], e.v[3]};
+            T fp[12], fm[12];
+            #pragma unroll
+            for (int i = 2; i <= 10; ++i) {
+                T f = (T)0.5 * nlT * u[i] * u[i];
+                fp[i] = (T)0.5 * (f + alpha * u[i]);
+                fm[i] = (T)0.5 * (f - alpha * u[i]);
+            }
+            #pragma unroll
+            for (int k = 0; k < 4; ++k)
+                F[q][k] = weno_face(fp[k + 2], fp[k + 3], fp[k + 4], fp[k + 5], fp[k + 6], eps) +
+                          weno_face(fm[k + 7], fm[k + 6], fm[k + 5], fm[k + 4], fm[k + 3], eps);
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active && c < Nc) q4[c] = quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}};
+    }
+    __syncthreads();
+    // b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau
+    const T mdt = -(T)(1.0 / d.dtau);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active && c < Nc) {
+            quad<T> f = q4[c];
+            T fprev = q4[(c - 1) & (Nc - 1)].v[3];
+            F[q][0] = mdt * (f.v[0] - fprev);
+            F[q][1] = mdt * (f.v[1] - f.v[0]);
+            F[q][2] = mdt * (f.v[2] - f.v[1]);
+            F[q][3] = mdt * (f.v[3] - f.v[2]);
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active && c < Nc) q4[c] = quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}};
+    }
+    __syncthreads();
+    lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
+    if (active) r2c_post(lds, base, Bout + so, M, t, tpr, tw, log2_ntw);
+}
+
+// ------------------------------------------------------------------ y-pass
+// A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows,
+// staged in LDS as lds[y * W + c]; W * n_y / 16 threads run the y-FFTs.
+// The multiplier tables are stored per tile as tab[m0 * Nh + n * W + c]
+// (n = |ky index|, the symbol is even in ky), pre-scaled by 1/n_y for the
+// inverse y-transform.  P is stored tile-contiguously at P[m0 * n_y + e].
+template <typename T, int NT, int STAGE>
+__global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
+                                               cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
+                                               cpx<T>* __restrict__ P, const cpx<T>* __restrict__ tabs,
+                                               const cpx<T>* __restrict__ tw, int log2_ntw) {
+    __shared__ alignas(32) cpx<T> lds[NT * 16];
+    const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstDesc& d = descs[it.inst];
+    const int Ny = d.n_y, M = d.M, W = d.W, lw = d.log2W, Nh = d.Nh;
+    const int m0 = it.m0;
+    const int tid = threadIdx.x;
+    const int nthr = W * (Ny >> 4);
+    const bool act = tid < nthr;
+    const int c = tid & (W - 1), t = tid >> lw;
+    const int ne = W * Ny;
+    const long long so = d.off_state;
+    const cpx<T>* Bt = B + so + m0;
+    cpx<T>* Ct = C + so + m0;
+    cpx<T>* Pt = P + so + (long long)m0 * Ny;
+    const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
+    const cpx<T>* tP1 = tE + d.tab_stride;
+    const cpx<T>* tP2 = tE + 2 * d.tab_stride;
+    const bool col0 = (m0 == 0);
+    const int half = Ny >> 1;
+
+    for (int e = tid; e < ne; e += NT) lds[e] = Bt[(long long)(e >> lw) * M + (e & (W - 1))];
+    __syncthreads();
+    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+
+    if (STAGE == 1) {
+        cpx<T> bh[16];
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + q * NT;
+            if (e < ne) bh[q] = lds[e];
+        }
+        __syncthreads();
+        for (int e = tid; e < ne; e += NT) lds[e] = Ct[(long long)(e >> lw) * M + (e & (W - 1))];
+        __syncthreads();
+        lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + q * NT;
+            if (e < ne) {
+                const int j = e >> lw, cc = e & (W - 1);
+                const int n = j <= half ? j : Ny - j;
+                const int ti = n * W + cc;
+                cpx<T> E = tE[ti], p1 = tP1[ti], p2 = tP2[ti];
+                cpx<T> U = lds[e];
+                cpx<T> EU = cmul(E, U);
+                cpx<T> Us = EU + cmul(p1, bh[q]);
+                cpx<T> Pv = EU + cmul(p1 - p2, bh[q]);
+                if (!(col0 && cc == 0)) Pt[e] = Pv;
+                lds[e] = Us;
+            }
+        }
+        __syncthreads();
+    } else {
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + q * NT;
+            if (e < ne) {
+                const int j = e >> lw, cc = e & (W - 1);
+                const int n = j <= half ? j : Ny - j;
+                lds[e] = Pt[e] + cmul(tP2[n * W + cc], lds[e]);
+            }
+        }
+        __syncthreads();
+    }
+    lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    for (int e = tid; e < ne; e += NT) {
+        const int cc = e & (W - 1);
+        if (!(col0 && cc == 0)) Ct[(long long)(e >> lw) * M + cc] = lds[e];
+    }
+    if (col0) {
+        // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
+        const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
+        for (int y = tid; y < Ny; y += NT) {
+            const cpx<T> b = Bt[(long long)y * M];
+            if (STAGE == 1) {
+                const cpx<T> cr = Ct[(long long)y * M];
+                Ct[(long long)y * M] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
+                Pt[(long long)y * W] = cpx<T>{cr.x, EN * cr.y + (P1N - P2N) * b.y};
+            } else {
+                const cpx<T> p = Pt[(long long)y * W];
+                Ct[(long long)y * M] = cpx<T>{p.x, p.y + P2N * b.y};
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ multiplier tables
+// phi-functions in FP64: Taylor series of phi2 (Horner) for |z| < 1, with
+// phi1 = 1 + z phi2 and e^z = 1 + z phi1; closed forms otherwise.
+__device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, cpx<double>& p2) {
+    const cpx<double> z = {zr, zi};
+    if (zr * zr + zi * zi < 1.0) {
+        // 1/(j+2)!, j = 0..20
+        double f = 1.0;
+        for (int j = 2; j <= 22; ++j) f *= (double)j;   // 22!
+        cpx<double> p = {1.0 / f, 0.0};
+        for (int j = 19; j >= 0; --j) {
+            f /= (double)(j + 3);                         // (j+2)!
+            p = cmul(z, p);
+            p.x += 1.0 / f;
+        }
+        p2 = p;
+        p1 = cmul(z, p2);
+        p1.x += 1.0;
+        e = cmul(z, p1);
+        e.x += 1.0;
+        return;
+    }
+    double ex = exp(zr), sn, cs;
+    sincos(zi, &sn, &cs);
+    e = {ex * cs, ex * sn};
+    const double inv = 1.0 / (zr * zr + zi * zi);
+    cpx<double> em1 = {e.x - 1.0, e.y};
+    p1 = inv * cmulc(em1, z);                 // (e^z - 1) / z
+    cpx<double> p1m1 = {p1.x - 1.0, p1.y};
+    p2 = inv * cmulc(p1m1, z);                // (phi1 - 1) / z
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                     cpx<T>* __restrict__ tabs, int step) {
+    const InstDesc& d = descs[inst];
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // storage order
+    if (o >= d.tab_size) return;
+    const int W = d.W, Nh = d.Nh;
+    const long long tile = o / ((long long)W * Nh);
+    const int rem = (int)(o - tile * W * Nh);
+    const int n = rem / W, c = rem - n * W;
+    const int m = (int)tile * W + c;
+    cpx<T>* tE = tabs + d.off_tab + o;
+    cpx<T>* tP1 = tE + d.tab_stride;
+    cpx<T>* tP2 = tE + 2 * d.tab_stride;
+    const double h = d.h;
+    cpx<double> e, p1, p2;
+    if (m == 0) {
+        if (n == 0) {   // tau-Nyquist scalars (absorption only), not scaled
+            const double kn = 2.0 * KZK_PI * (double)(-d.M) / d.L_tau;
+            phis_f64(-h * d.A * kn * kn, 0.0, e, p1, p2);
+            *tE = cpx<T>{(T)e.x, (T)0};
+            *tP1 = cpx<T>{(T)(h * p1.x), (T)0};
+            *tP2 = cpx<T>{(T)(h * p2.x), (T)0};
+        } else {
+            *tE = *tP1 = *tP2 = cpx<T>{(T)0, (T)0};
+        }
+        return;
+    }
+    const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
+    const double kt = 2.0 * KZK_PI * (double)m / d.L_tau;
+    const double ky = 2.0 * KZK_PI * (double)n / d.L_y;
+    // z = h l,  l = i Dbar ky^2 / (2 kt) - A kt^2
+    phis_f64(-h * d.A * kt * kt, h * Dbar * ky * ky / (2.0 * kt), e, p1, p2);
+    const double s = 1.0 / (double)d.n_y;
+    *tE = cpx<T>{(T)(e.x * s), (T)(e.y * s)};
+    *tP1 = cpx<T>{(T)(h * s * p1.x), (T)(h * s * p1.y)};
+    *tP2 = cpx<T>{(T)(h * s * p2.x), (T)(h * s * p2.y)};
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+                      T* u_out, const void* Cin, void* Bout, const void* tw, int log2_ntw, int node,
+                      unsigned* status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    dim3 g(n_items), b(TAU_THREADS);
+    const cpx<T>* ci = static_cast<const cpx<T>*>(Cin);
+    cpx<T>* bo = static_cast<cpx<T>*>(Bout);
+    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
+    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
+                              const void* B, void* P, const void* tabs, const void* tw, int log2_ntw,
+                              hipStream_t s) {
+    dim3 g(n_items), b(NT);
+    cpx<T>* c = static_cast<cpx<T>*>(C);
+    const cpx<T>* bb = static_cast<const cpx<T>*>(B);
+    cpx<T>* p = static_cast<cpx<T>*>(P);
+    const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
+    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    if (stage == 1)
+        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, tb, w, log2_ntw);
+    else
+        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, tb, w, log2_ntw);
+    return hipGetLastError();
+}
+
+bool y_threads_supported(int is_f64, int nt) {
+    if (nt == 256 || nt == 512) return true;
+    return nt == 1024 && !is_f64;
+}
+
+template <typename T>
+hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
+                    const void* B, void* P, const void* tabs, const void* tw, int log2_ntw, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (nt) {
+    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
+    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
+    case 1024:
+        if constexpr (sizeof(T) == 4)
+            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step, hipStream_t s) {
+    if (n_elems <= 0) return hipSuccess;
+    dim3 g((n_elems + 255) / 256), b(256);
+    hipLaunchKernelGGL((tables_kernel<T>), g, b, 0, s, d_desc, inst, static_cast<cpx<T>*>(tabs), step);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tau<float>(int, const InstDesc*, const TauItem*, int, const float*, float*, const void*,
+                                      void*, const void*, int, int, unsigned*, hipStream_t);
+template hipError_t launch_tau<double>(int, const InstDesc*, const TauItem*, int, const double*, double*,
+                                       const void*, void*, const void*, int, int, unsigned*, hipStream_t);
+template hipError_t launch_y<float>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
+                                    const void*, const void*, int, hipStream_t);
+template hipError_t launch_y<double>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
+                                     const void*, const void*, int, hipStream_t);
+template hipError_t launch_tables<float>(const InstDesc*, int, int, void*, int, hipStream_t);
+template hipError_t launch_tables<double>(const InstDesc*, int, int, void*, int, hipStream_t);
+
+}  // namespace kzk

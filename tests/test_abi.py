@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function declared in include/kzk.h, and argument errors are rejected
+before anything touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "kzk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kzk_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_destroy", "kzk_inst_offset",
+              "kzk_status_str"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_06080_amd import kzk
+    L = kzk.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    assert sorted(kzk.EXPORTS) == declared_functions()
+
+
+def test_status_strings():
+    from paper_2103_06080_amd import kzk
+    L = kzk.lib()
+    for code in range(8):
+        assert L.kzk_status_str(code)
+
+
+def _params(**kw):
+    from paper_2103_06080_amd import kzk
+    base = dict(n_tau=64, n_y=32, tau0=-4.0, L_tau=8.0, y0=-8.0, L_y=16.0, x0=0.0, h=1e-3, dtype=1,
+                D=0.05, A=0.0, nl=1.0, D_step=None, nl_node=None, n_steps_max=0, lf_scope=0,
+                weno_eps=1e-6, cfl_max=1.0)
+    base.update(kw)
+    null = ctypes.POINTER(ctypes.c_double)()
+    return kzk.Params(base["n_tau"], base["n_y"], base["tau0"], base["L_tau"], base["y0"], base["L_y"],
+                      base["x0"], base["h"], base["dtype"], base["D"], base["A"], base["nl"], null, null,
+                      base["n_steps_max"], base["lf_scope"], base["weno_eps"], base["cfl_max"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_tau=48), 2), (dict(n_tau=16), 2), (dict(n_tau=16384), 2), (dict(n_y=8), 2), (dict(n_y=8192), 2),
+    (dict(h=0.0), 1), (dict(h=-1.0), 1), (dict(L_tau=0.0), 1), (dict(dtype=3), 1), (dict(A=-1.0), 1),
+    (dict(weno_eps=0.0), 1), (dict(lf_scope=1), 1), (dict(cfl_max=-1.0), 1),
+])
+def test_create_rejects_bad_parameters_before_device_work(kw, code):
+    from paper_2103_06080_amd import kzk
+    L = kzk.lib()
+    p = _params(**kw)
+    h = ctypes.c_void_p()
+    assert L.kzk_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == code
+    assert not h.value
+
+
+def test_null_arguments_rejected():
+    from paper_2103_06080_amd import kzk
+    L = kzk.lib()
+    h = ctypes.c_void_p()
+    assert L.kzk_create(None, 1, None, ctypes.byref(h)) == 1
+    p = _params()
+    assert L.kzk_create(ctypes.byref(p), 0, None, ctypes.byref(h)) == 1
+    assert L.kzk_step(None, None, 0, 1) == 1
+    assert L.kzk_poll(None) == 1
+    assert L.kzk_adjoint(None, None, None, 0, 1, 1, None) == 1
+    assert L.kzk_inst_offset(None, 0) == ctypes.c_size_t(-1).value
