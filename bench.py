@@ -90,6 +90,10 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    ap.add_argument("--y-threads", type=int, default=0, help="y-pass block size (0: plan default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for memory counters)")
+    ap.add_argument("--march-steps", type=int, default=0, help="override the steps of one march (profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -102,12 +106,20 @@ def main():
     from paper_2103_06080_amd import inputs, kzk
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     base = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config]()
-    steps_per_march = base.n_steps
+    steps_per_march = args.march_steps or base.n_steps
     total = steps_per_march * (args.warmup + args.steps)
     prob = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config](n_steps=total)
 
-    plan = kzk.Plan(prob, dtype=args.dtype)
+    plan = kzk.Plan(prob, dtype=args.dtype, y_threads=args.y_threads or None)
     u = plan.pack([prob.u0])
     torch.cuda.synchronize()
 

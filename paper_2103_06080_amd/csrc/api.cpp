@@ -168,13 +168,16 @@ kzk_status build_tables(kzk_plan* p, int step, bool only_scheduled) {
     return KZK_OK;
 }
 
-hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void* Cin, void* Bout, int node) {
+// tiled = 1: spectra in the column-tile layout of the y-pass (internal arrays);
+// tiled = 0: row-major spectra (the single-operator transform entries).
+hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void* Cin, void* Bout, int node,
+               int tiled = 1) {
     ProfScope ps(p, mode == 2 ? KZK_KIND_TAU : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_tau<float>(mode, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in, (float*)u_out,
-                                      Cin, Bout, p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+                                      Cin, Bout, p->dTw, p->log2_ntw, node, tiled, p->dStatus, p->stream);
     return kzk::launch_tau<double>(mode, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in, (double*)u_out,
-                                   Cin, Bout, p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+                                   Cin, Bout, p->dTw, p->log2_ntw, node, tiled, p->dStatus, p->stream);
 }
 
 hipError_t ypass(kzk_plan* p, int stage) {
@@ -486,12 +489,12 @@ kzk_status kzk_eval_b(kzk_plan* p, const void* u, int32_t node, void* b) {
 
 kzk_status kzk_tau_forward(kzk_plan* p, const void* u, void* spec) {
     if (!p || !u || !spec) return KZK_ERR_ARG;
-    return tau(p, 0, u, nullptr, nullptr, spec, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+    return tau(p, 0, u, nullptr, nullptr, spec, 0, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
 }
 
 kzk_status kzk_tau_inverse(kzk_plan* p, const void* spec, void* u) {
     if (!p || !u || !spec) return KZK_ERR_ARG;
-    return tau(p, 1, nullptr, u, spec, nullptr, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+    return tau(p, 1, nullptr, u, spec, nullptr, 0, 0) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
 }
 
 kzk_status kzk_read_tables(kzk_plan* p, int32_t inst, void* out) {

@@ -111,6 +111,13 @@ template <int S, typename T> __device__ __forceinline__ cpx<T> twiddle(const cpx
     return S > 0 ? cpx<T>{w.x, -w.y} : w;
 }
 
+// ---------------------------------------------------------------- LDS layout
+// Logical LDS index -> physical slot: one pad slot after every 16 complex
+// values, so that accesses at a stride of 16 (the first Stockham stage, and
+// the y-pass tiles) spread over all banks instead of hitting one.
+__device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + n / 16; }
+
 // ---------------------------------------------------------------- one Stockham stage
 // Length-n transform stored at buf[base + idx * stride].  Thread t (< n/16)
 // takes butterflies j = t + b * n/16... for b < 16/R; the stage reads the
@@ -128,7 +135,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int base, int stride
         for (int b = 0; b < PER; ++b) {
             int j = t + b * tpr;
             #pragma unroll
-            for (int s = 0; s < R; ++s) v[b][s] = buf[base + (j + s * nR) * stride];
+            for (int s = 0; s < R; ++s) v[b][s] = buf[padi(base + (j + s * nR) * stride)];
         }
     }
     __syncthreads();
@@ -145,7 +152,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int base, int stride
             Dft<T, R, S>::run(v[b]);
             int d = (j - k) * R + k;
             #pragma unroll
-            for (int s = 0; s < R; ++s) buf[base + (d + s * Ns) * stride] = v[b][s];
+            for (int s = 0; s < R; ++s) buf[padi(base + (d + s * Ns) * stride)] = v[b][s];
         }
     }
     __syncthreads();
@@ -153,8 +160,8 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* buf, int base, int stride
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
-// Full in-place length-n FFT (16 <= n <= 8192) of the sequence at
-// buf[base + idx * stride], done by threads t < n/16 where `active`.
+// Full in-place length-n FFT (16 <= n <= 8192) of the sequence at logical
+// LDS positions base + idx * stride, done by threads t < n/16 where `active`.
 // log2_ntw = log2 of the twiddle table length (>= log2 n).
 template <typename T, int S>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int stride, int n, int t, bool active,

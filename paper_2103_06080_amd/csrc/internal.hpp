@@ -40,7 +40,7 @@ struct YItem { int inst, m0; };
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items,
                       const T* u_in, T* u_out, const void* Cin, void* Bout, const void* tw,
-                      int log2_ntw, int node, unsigned* status, hipStream_t s);
+                      int log2_ntw, int node, int tiled, unsigned* status, hipStream_t s);
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,

@@ -26,6 +26,20 @@ constexpr double KZK_PI = 3.14159265358979323846264338327950288;
 
 template <typename T> struct alignas(4 * sizeof(T)) quad { T v[4]; };
 
+// Four consecutive reals of a line buffer = two complex slots 2c, 2c+1 of
+// the row starting at logical index base (base + 2c is even, so the pair
+// never straddles a pad slot).
+template <typename T> __device__ __forceinline__ quad<T> lds_quad(const cpx<T>* lds, int base, int c) {
+    const int i = padi(base + 2 * c);
+    cpx<T> a = lds[i], b = lds[i + 1];
+    return quad<T>{{a.x, a.y, b.x, b.y}};
+}
+template <typename T> __device__ __forceinline__ void lds_quad_st(cpx<T>* lds, int base, int c, quad<T> q) {
+    const int i = padi(base + 2 * c);
+    lds[i] = cpx<T>{q.v[0], q.v[1]};
+    lds[i + 1] = cpx<T>{q.v[2], q.v[3]};
+}
+
 template <typename T> __device__ __forceinline__ T rcp(T x);
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double rcp<double>(double x) {
@@ -121,37 +135,47 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 //   A = (Z_k + conj Z_{M-k})/2,  Q = i e^{-2 pi i k/N} (Z_k - conj Z_{M-k})/2,
 //   X_k = A - Q,  X_{M-k} = conj(A + Q),  slot 0 = (X_0, X_M).
 
+// Position of tau-mode k of one row in a spectral array: row-major rows of M
+// modes, or column tiles [k / W][y][k % W] (tile = W modes x n_y rows).
+struct SpecIdx {
+    int lw;
+    long long tile_stride;   // n_y * W for tiles, 0 for row-major
+    __device__ __forceinline__ long long operator()(int k) const {
+        return tile_stride ? (long long)(k >> lw) * tile_stride + (k & ((1 << lw) - 1)) : (long long)k;
+    }
+};
+
 template <typename T>
-__device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, cpx<T>* lds, int base, int M, int t, int tpr,
-                                        const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
+__device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int M, int t,
+                                        int tpr, const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
     const int lg_n = ilog2(2 * M);
     for (int k = t; k <= (M >> 1); k += tpr) {
         if (k == 0) {
             cpx<T> s = X[0];
-            lds[base] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
+            lds[padi(base)] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
             continue;
         }
-        cpx<T> xk = X[k], xm = X[M - k];
+        cpx<T> xk = X[ix(k)], xm = X[ix(M - k)];
         cpx<T> A = {xk.x + xm.x, xk.y - xm.y};
         cpx<T> D = {xk.x - xm.x, xk.y + xm.y};
         cpx<T> w = conj(tw[k << (log2_ntw - lg_n)]);      // e^{+2 pi i k/N}
         cpx<T> P = mul_si<1>(cmul(w, D));
         cpx<T> zk = A + P;
-        lds[base + k] = inv_n * zk;
+        lds[padi(base + k)] = inv_n * zk;
         if (2 * k != M) {
             cpx<T> zm = conj(A - P);
-            lds[base + M - k] = inv_n * zm;
+            lds[padi(base + M - k)] = inv_n * zm;
         }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, int M, int t, int tpr,
-                                         const cpx<T>* __restrict__ tw, int log2_ntw) {
+__device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int M, int t,
+                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw) {
     const int lg_n = ilog2(2 * M);
     for (int k = t; k <= (M >> 1); k += tpr) {
-        cpx<T> zk = lds[base + k];
-        cpx<T> zm = lds[base + ((M - k) & (M - 1))];
+        cpx<T> zk = lds[padi(base + k)];
+        cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
         cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
         cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
         cpx<T> w = tw[k << (log2_ntw - lg_n)];             // e^{-2 pi i k/N}
@@ -160,8 +184,8 @@ __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __
             X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
             continue;
         }
-        X[k] = A - Q;
-        if (2 * k != M) X[M - k] = conj(A + Q);
+        X[ix(k)] = A - Q;
+        if (2 * k != M) X[ix(M - k)] = conj(A + Q);
     }
 }
 
@@ -172,11 +196,12 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
                                                           const T* __restrict__ u_in, T* __restrict__ u_out,
                                                           const cpx<T>* __restrict__ Cin, cpx<T>* __restrict__ Bout,
                                                           const cpx<T>* __restrict__ tw, int log2_ntw, int node,
-                                                          unsigned* __restrict__ status) {
-    __shared__ alignas(32) cpx<T> lds[TAU_THREADS * 16];
+                                                          int tiled, unsigned* __restrict__ status) {
+    __shared__ alignas(32) cpx<T> lds[padded(TAU_THREADS * 16)];
     __shared__ T redT[4];
     __shared__ int redI[4];
-    const TauItem it = items[blockIdx.x];
+    // consecutive rows on one XCD: with column tiles, rows y..y+W-1 share cache lines
+    const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
     const int M = d.M, N = 2 * M;
     const int tpr = M >> 4;
@@ -185,8 +210,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
     const int base = r * M;
     const int Nc = M >> 1;   // chunks of 4 reals per line
-    quad<T>* q4 = reinterpret_cast<quad<T>*>(lds + base);
-    const long long so = d.off_state + (long long)row * M;
+    const SpecIdx ix = {d.log2W, tiled ? (long long)d.n_y << d.log2W : 0};
+    const long long so = d.off_state + (tiled ? ((long long)row << d.log2W) : (long long)row * M);
 
     if (MODE == 0) {
         const quad<T>* ug = reinterpret_cast<const quad<T>*>(u_in + d.off_u + (long long)row * N);
@@ -195,25 +220,25 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
             for (int c = t; c < Nc; c += tpr) {
                 quad<T> v = ug[c];
                 bad |= !(finite_val(v.v[0]) && finite_val(v.v[1]) && finite_val(v.v[2]) && finite_val(v.v[3]));
-                q4[c] = v;
+                lds_quad_st(lds, base, c, v);
             }
         bad = line_or(bad, tpr, redI);
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
         lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
-        if (active) r2c_post(lds, base, Bout + so, M, t, tpr, tw, log2_ntw);
+        if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
         return;
     }
 
     // inverse tau-transform of C~ into the line buffer
-    if (active) c2r_pre(Cin + so, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    if (active) c2r_pre(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
     __syncthreads();
     lds_fft<T, 1>(lds, base, 1, M, t, active, tw, log2_ntw);
 
     if (MODE == 1) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
         if (active)
-            for (int c = t; c < Nc; c += tpr) ug[c] = q4[c];
+            for (int c = t; c < Nc; c += tpr) ug[c] = lds_quad(lds, base, c);
         return;
     }
 
@@ -222,7 +247,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     int bad = 0;
     if (active)
         for (int c = t; c < Nc; c += tpr) {
-            quad<T> v = q4[c];
+            quad<T> v = lds_quad(lds, base, c);
             #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 bad |= !finite_val(v.v[i]);
@@ -248,7 +273,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
         if (active && c < Nc) {
-            quad<T> a = q4[(c - 1) & (Nc - 1)], b = q4[c], e = q4[(c + 1) & (Nc - 1)];
+            quad<T> a = lds_quad(lds, base, (c - 1) & (Nc - 1)), b = lds_quad(lds, base, c),
+                    e = lds_quad(lds, base, (c + 1) & (Nc - 1));
             T u[12] = {a.v[0], a.v[1], a.v[2], a.v[3], b.v[0], b.v[1], b.v[2], b.v[3],
                        e.v[0], e.v[1], e.v[2], e.v[3]};
             T fp[12], fm[12];
@@ -268,7 +294,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
-        if (active && c < Nc) q4[c] = quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}};
+        if (active && c < Nc) lds_quad_st(lds, base, c, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
     }
     __syncthreads();
     // b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau
@@ -277,8 +303,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
         if (active && c < Nc) {
-            quad<T> f = q4[c];
-            T fprev = q4[(c - 1) & (Nc - 1)].v[3];
+            quad<T> f = lds_quad(lds, base, c);
+            T fprev = lds_quad(lds, base, (c - 1) & (Nc - 1)).v[3];
             F[q][0] = mdt * (f.v[0] - fprev);
             F[q][1] = mdt * (f.v[1] - f.v[0]);
             F[q][2] = mdt * (f.v[2] - f.v[1]);
@@ -289,16 +315,18 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
-        if (active && c < Nc) q4[c] = quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}};
+        if (active && c < Nc) lds_quad_st(lds, base, c, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
     }
     __syncthreads();
     lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
-    if (active) r2c_post(lds, base, Bout + so, M, t, tpr, tw, log2_ntw);
+    if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
 }
 
 // ------------------------------------------------------------------ y-pass
-// A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows,
-// staged in LDS as lds[y * W + c]; W * n_y / 16 threads run the y-FFTs.
+// A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows.
+// The spectra C~, B~ are stored in column tiles [m / W][y][m % W], so the
+// tile is one contiguous block of W * n_y values, staged in LDS in the same
+// order (lds[y * W + c]); W * n_y / 16 threads run the y-FFTs.
 // The multiplier tables are stored per tile as tab[m0 * Nh + n * W + c]
 // (n = |ky index|, the symbol is even in ky), pre-scaled by 1/n_y for the
 // inverse y-transform.  P is stored tile-contiguously at P[m0 * n_y + e].
@@ -307,10 +335,10 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
                                                cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
                                                cpx<T>* __restrict__ P, const cpx<T>* __restrict__ tabs,
                                                const cpx<T>* __restrict__ tw, int log2_ntw) {
-    __shared__ alignas(32) cpx<T> lds[NT * 16];
+    __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
-    const int Ny = d.n_y, M = d.M, W = d.W, lw = d.log2W, Nh = d.Nh;
+    const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
     const int m0 = it.m0;
     const int tid = threadIdx.x;
     const int nthr = W * (Ny >> 4);
@@ -318,8 +346,8 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     const int c = tid & (W - 1), t = tid >> lw;
     const int ne = W * Ny;
     const long long so = d.off_state;
-    const cpx<T>* Bt = B + so + m0;
-    cpx<T>* Ct = C + so + m0;
+    const cpx<T>* Bt = B + so + (long long)m0 * Ny;
+    cpx<T>* Ct = C + so + (long long)m0 * Ny;
     cpx<T>* Pt = P + so + (long long)m0 * Ny;
     const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
     const cpx<T>* tP1 = tE + d.tab_stride;
@@ -327,7 +355,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     const bool col0 = (m0 == 0);
     const int half = Ny >> 1;
 
-    for (int e = tid; e < ne; e += NT) lds[e] = Bt[(long long)(e >> lw) * M + (e & (W - 1))];
+    for (int e = tid; e < ne; e += NT) lds[padi(e)] = Bt[e];
     __syncthreads();
     lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
 
@@ -336,10 +364,10 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
         #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + q * NT;
-            if (e < ne) bh[q] = lds[e];
+            if (e < ne) bh[q] = lds[padi(e)];
         }
         __syncthreads();
-        for (int e = tid; e < ne; e += NT) lds[e] = Ct[(long long)(e >> lw) * M + (e & (W - 1))];
+        for (int e = tid; e < ne; e += NT) lds[padi(e)] = Ct[e];
         __syncthreads();
         lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
         #pragma unroll
@@ -350,12 +378,12 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
                 const int n = j <= half ? j : Ny - j;
                 const int ti = n * W + cc;
                 cpx<T> E = tE[ti], p1 = tP1[ti], p2 = tP2[ti];
-                cpx<T> U = lds[e];
+                cpx<T> U = lds[padi(e)];
                 cpx<T> EU = cmul(E, U);
                 cpx<T> Us = EU + cmul(p1, bh[q]);
                 cpx<T> Pv = EU + cmul(p1 - p2, bh[q]);
                 if (!(col0 && cc == 0)) Pt[e] = Pv;
-                lds[e] = Us;
+                lds[padi(e)] = Us;
             }
         }
         __syncthreads();
@@ -366,7 +394,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
             if (e < ne) {
                 const int j = e >> lw, cc = e & (W - 1);
                 const int n = j <= half ? j : Ny - j;
-                lds[e] = Pt[e] + cmul(tP2[n * W + cc], lds[e]);
+                lds[padi(e)] = Pt[e] + cmul(tP2[n * W + cc], lds[padi(e)]);
             }
         }
         __syncthreads();
@@ -374,20 +402,20 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
     for (int e = tid; e < ne; e += NT) {
         const int cc = e & (W - 1);
-        if (!(col0 && cc == 0)) Ct[(long long)(e >> lw) * M + cc] = lds[e];
+        if (!(col0 && cc == 0)) Ct[e] = lds[padi(e)];
     }
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
         const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
         for (int y = tid; y < Ny; y += NT) {
-            const cpx<T> b = Bt[(long long)y * M];
+            const cpx<T> b = Bt[(long long)y * W];
             if (STAGE == 1) {
-                const cpx<T> cr = Ct[(long long)y * M];
-                Ct[(long long)y * M] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
+                const cpx<T> cr = Ct[(long long)y * W];
+                Ct[(long long)y * W] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
                 Pt[(long long)y * W] = cpx<T>{cr.x, EN * cr.y + (P1N - P2N) * b.y};
             } else {
                 const cpx<T> p = Pt[(long long)y * W];
-                Ct[(long long)y * M] = cpx<T>{p.x, p.y + P2N * b.y};
+                Ct[(long long)y * W] = cpx<T>{p.x, p.y + P2N * b.y};
             }
         }
     }
@@ -468,7 +496,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
 
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
-                      T* u_out, const void* Cin, void* Bout, const void* tw, int log2_ntw, int node,
+                      T* u_out, const void* Cin, void* Bout, const void* tw, int log2_ntw, int node, int tiled,
                       unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     dim3 g(n_items), b(TAU_THREADS);
@@ -476,9 +504,9 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
     cpx<T>* bo = static_cast<cpx<T>*>(Bout);
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
-    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
-    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, status); break;
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
+    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -530,9 +558,9 @@ hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* ta
 }
 
 template hipError_t launch_tau<float>(int, const InstDesc*, const TauItem*, int, const float*, float*, const void*,
-                                      void*, const void*, int, int, unsigned*, hipStream_t);
+                                      void*, const void*, int, int, int, unsigned*, hipStream_t);
 template hipError_t launch_tau<double>(int, const InstDesc*, const TauItem*, int, const double*, double*,
-                                       const void*, void*, const void*, int, int, unsigned*, hipStream_t);
+                                       const void*, void*, const void*, int, int, int, unsigned*, hipStream_t);
 template hipError_t launch_y<float>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
                                     const void*, const void*, int, hipStream_t);
 template hipError_t launch_y<double>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
