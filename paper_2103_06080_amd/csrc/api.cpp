@@ -62,8 +62,8 @@ struct kzk_plan {
     std::vector<Ev> ev_used;
     std::vector<hipEvent_t> ev_pool;
 
-    // adjoint workspace (allocated on first use)
-    void *dL = nullptr, *dMu = nullptr, *dCk = nullptr, *dUn = nullptr, *dUs = nullptr, *dT = nullptr;
+    // adjoint workspace (allocated on first use, grown on demand)
+    void *dL = nullptr, *dM = nullptr, *dR = nullptr, *dCk = nullptr, *dUn = nullptr, *dUs = nullptr;
     size_t adj_ckpt_cap = 0, adj_seg_cap = 0;
 };
 
@@ -202,6 +202,24 @@ kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
         if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
     }
     return KZK_OK;
+}
+
+hipError_t tau_adj(kzk_plan* p, int stage, const void* Tin, const void* Rin, const void* ustore, void* out, int node) {
+    ProfScope ps(p, KZK_KIND_ADJ_TAU);
+    if (p->dtype == KZK_F32)
+        return kzk::launch_tau_adj<float>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const float*)ustore, out,
+                                          p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+    return kzk::launch_tau_adj<double>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const double*)ustore, out,
+                                       p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+}
+
+hipError_t y_adj(kzk_plan* p, int stage, const void* In, void* Lh, void* Tout, void* Rout) {
+    ProfScope ps(p, KZK_KIND_ADJ_Y);
+    if (p->dtype == KZK_F32)
+        return kzk::launch_y_adj<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout,
+                                        p->dTab, p->dTw, p->log2_ntw, p->stream);
+    return kzk::launch_y_adj<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout, p->dTab,
+                                     p->dTw, p->log2_ntw, p->stream);
 }
 
 kzk_status enqueue_march(kzk_plan* p, void* u, int first, int n) {
@@ -518,11 +536,89 @@ kzk_status kzk_read_tables(kzk_plan* p, int32_t inst, void* out) {
     return hipMemcpy(out, lin.data(), lin.size(), hipMemcpyHostToDevice) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
 }
 
-kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n, int32_t ckpt,
-                       void* grad) {
-    (void)u0; (void)lam; (void)first; (void)n; (void)ckpt; (void)grad;
-    if (!p) return KZK_ERR_ARG;
-    return KZK_ERR_STATE;
+}  // extern "C"
+
+namespace {
+
+// Grow the adjoint workspace: three spectra, ckpt physical fields for u^n
+// and for u*, and nseg checkpoints of the spectral state.
+kzk_status adjoint_workspace(kzk_plan* p, size_t ckpt, size_t nseg) {
+    const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;
+    if (!p->dL) {
+        kzk_status st;
+        if ((st = dev_alloc(p, &p->dL, sb)) != KZK_OK || (st = dev_alloc(p, &p->dM, sb)) != KZK_OK ||
+            (st = dev_alloc(p, &p->dR, sb)) != KZK_OK)
+            return st;
+    }
+    if (ckpt > p->adj_ckpt_cap) {
+        kzk_status st;
+        if ((st = dev_alloc(p, &p->dUn, ckpt * ub)) != KZK_OK || (st = dev_alloc(p, &p->dUs, ckpt * ub)) != KZK_OK)
+            return st;
+        p->adj_ckpt_cap = ckpt;
+    }
+    if (nseg > p->adj_seg_cap) {
+        kzk_status st = dev_alloc(p, &p->dCk, nseg * sb);
+        if (st != KZK_OK) return st;
+        p->adj_seg_cap = nseg;
+    }
+    return KZK_OK;
 }
 
-}  // extern "C"
+}  // namespace
+
+extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
+                                  int32_t ckpt, void* grad) {
+    if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
+    kzk_status st = check_range(p, first, n);
+    if (st != KZK_OK) return st;
+    const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;
+    if (n == 0) {
+        if (grad != lam && hipMemcpyAsync(grad, lam, ub, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            return KZK_ERR_DEVICE;
+        return KZK_OK;
+    }
+    const int K = std::min<int>(ckpt, n);
+    const int nseg = (n + K - 1) / K;
+    if ((st = adjoint_workspace(p, (size_t)K, (size_t)nseg)) != KZK_OK) return st;
+    char* ck = (char*)p->dCk;
+    char* Un = (char*)p->dUn;
+    char* Us = (char*)p->dUs;
+
+    // forward sweep, keeping the spectral state at the start of every segment
+    if (tau(p, 0, u0, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    for (int g = 0; g < nseg; ++g) {
+        const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
+        if (hipMemcpyAsync(ck + (size_t)g * sb, p->dC, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            return KZK_ERR_DEVICE;
+        if ((st = enqueue_steps(p, s0, s1 - s0)) != KZK_OK) return st;
+    }
+    // adjoint state L~ = tau-spectrum of dL/du at the end
+    if (tau(p, 0, lam, nullptr, nullptr, p->dL, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    for (int g = nseg - 1; g >= 0; --g) {
+        const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
+        if (hipMemcpyAsync(p->dC, ck + (size_t)g * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            return KZK_ERR_DEVICE;
+        // recompute the segment, storing u^n and u* in physical space
+        for (int s = s0; s < s1; ++s) {
+            if (p->any_D_sched && (st = build_tables(p, s, true)) != KZK_OK) return st;
+            if (tau(p, 3, nullptr, Un + (size_t)(s - s0) * ub, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
+            if (ypass(p, 1) != hipSuccess) return KZK_ERR_DEVICE;
+            if (tau(p, 3, nullptr, Us + (size_t)(s - s0) * ub, p->dC, p->dB, s + 1) != hipSuccess)
+                return KZK_ERR_DEVICE;
+            if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
+        }
+        // adjoint steps back through the segment
+        for (int s = s1 - 1; s >= s0; --s) {
+            if (p->any_D_sched && (st = build_tables(p, s, true)) != KZK_OK) return st;
+            if (y_adj(p, 1, p->dL, p->dP, p->dB, nullptr) != hipSuccess) return KZK_ERR_DEVICE;
+            if (tau_adj(p, 1, p->dB, nullptr, Us + (size_t)(s - s0) * ub, p->dM, s + 1) != hipSuccess)
+                return KZK_ERR_DEVICE;
+            if (y_adj(p, 2, p->dM, p->dP, p->dB, p->dR) != hipSuccess) return KZK_ERR_DEVICE;
+            if (tau_adj(p, 2, p->dB, p->dR, Un + (size_t)(s - s0) * ub, p->dL, s) != hipSuccess)
+                return KZK_ERR_DEVICE;
+        }
+    }
+    if (tau(p, 1, nullptr, grad, p->dL, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+

@@ -51,6 +51,16 @@ template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step,
                          hipStream_t s);
 
+template <typename T>
+hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
+                          const void* Rin, const T* ustore, void* out, const void* tw, int log2_ntw, int node,
+                          unsigned* status, hipStream_t s);
+
+template <typename T>
+hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
+                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
+                        hipStream_t s);
+
 // Block sizes of the y-pass for which kernels are compiled.
 bool y_threads_supported(int dtype_is_f64, int nt);
 

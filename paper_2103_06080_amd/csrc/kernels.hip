@@ -190,6 +190,7 @@ __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __
 }
 
 // MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B (b via WENO5).
+// MODE 3: as MODE 2, and also stores the physical line u (for the adjoint).
 template <typename T, int MODE>
 __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __restrict__ descs,
                                                           const TauItem* __restrict__ items,
@@ -235,11 +236,11 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     __syncthreads();
     lds_fft<T, 1>(lds, base, 1, M, t, active, tw, log2_ntw);
 
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 3) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
         if (active)
             for (int c = t; c < Nc; c += tpr) ug[c] = lds_quad(lds, base, c);
-        return;
+        if (MODE == 1) return;
     }
 
     // ---- LF speed alpha = |nl(x_node)| max|u| over the line (exact in any precision)
@@ -421,6 +422,344 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     }
 }
 
+
+// ------------------------------------------------------------------ adjoint
+// Transpose of the step map u^n -> u^{n+1} (ExpRK22, Sec. 3.3 eq. (19)) on
+// real fields.  With Ecal = F^-1 E F, Pk = F^-1 Phi_k Z F (Z zeroes the mean
+// tau-mode) and J0, J1 the Jacobians of b at (x_n, u^n) and (x_{n+1}, u*):
+//     mu    = h J1^T P2^T lam
+//     lam_n = Ecal^T (lam + mu) + h J0^T [ (P1 - P2)^T lam + P1^T mu ].
+// The transpose of a Fourier multiplier is the multiplier with the complex
+// conjugate symbol (the symbol is Hermitian), so the adjoint reuses the tables.
+
+// Sum over the tpr threads of one line (same grouping as line_max).
+template <typename T>
+__device__ __forceinline__ T line_sum(T v, int tpr, T* red) {
+    const int w = tpr < 64 ? tpr : 64;
+    for (int o = w >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (tpr > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = v;
+        __syncthreads();
+        const int nw = tpr >> 6, first = (threadIdx.x / tpr) * nw;
+        T m = red[first];
+        for (int i = 1; i < nw; ++i) m += red[first + i];
+        v = m;
+        __syncthreads();
+    }
+    return v;
+}
+
+// Gradient of weno_face with respect to v0..v4:
+//   dF/dv_k = sum_r w_r dq_r/dv_k + sum_r c_r dbeta_r/dv_k,
+//   c_r = -2 (q_r - F) w_r / (eps + beta_r),  w_r the nonlinear weights.
+template <typename T>
+__device__ __forceinline__ void weno_face_grad(T v0, T v1, T v2, T v3, T v4, T eps, T g[5]) {
+    const T c1312 = (T)(13.0 / 12.0), c136 = (T)(13.0 / 6.0), s6 = (T)(1.0 / 6.0);
+    T q0 = ((T)2 * v0 - (T)7 * v1 + (T)11 * v2) * s6;
+    T q1 = (-v1 + (T)5 * v2 + (T)2 * v3) * s6;
+    T q2 = ((T)2 * v2 + (T)5 * v3 - v4) * s6;
+    T A0 = v0 - (T)2 * v1 + v2, B0 = v0 - (T)4 * v1 + (T)3 * v2;
+    T A1 = v1 - (T)2 * v2 + v3, B1 = v1 - v3;
+    T A2 = v2 - (T)2 * v3 + v4, B2 = (T)3 * v2 - (T)4 * v3 + v4;
+    T r0 = rcp(eps + c1312 * A0 * A0 + (T)0.25 * B0 * B0);
+    T r1 = rcp(eps + c1312 * A1 * A1 + (T)0.25 * B1 * B1);
+    T r2 = rcp(eps + c1312 * A2 * A2 + (T)0.25 * B2 * B2);
+    T a0 = (T)0.1 * r0 * r0, a1 = (T)0.6 * r1 * r1, a2 = (T)0.3 * r2 * r2;
+    T iS = rcp(a0 + a1 + a2);
+    T w0 = a0 * iS, w1 = a1 * iS, w2 = a2 * iS;
+    T F = w0 * q0 + w1 * q1 + w2 * q2;
+    T c0 = (T)-2 * (q0 - F) * w0 * r0;
+    T c1 = (T)-2 * (q1 - F) * w1 * r1;
+    T c2 = (T)-2 * (q2 - F) * w2 * r2;
+    T e0 = c136 * A0 * c0, f0 = (T)0.5 * B0 * c0;
+    T e1 = c136 * A1 * c1, f1 = (T)0.5 * B1 * c1;
+    T e2 = c136 * A2 * c2, f2 = (T)0.5 * B2 * c2;
+    g[0] = (T)2 * s6 * w0 + e0 + f0;
+    g[1] = (T)-7 * s6 * w0 - s6 * w1 - (T)2 * e0 - (T)4 * f0 + e1 + f1;
+    g[2] = (T)11 * s6 * w0 + (T)5 * s6 * w1 + (T)2 * s6 * w2 + e0 + (T)3 * f0 - (T)2 * e1 + e2 + (T)3 * f2;
+    g[3] = (T)2 * s6 * w1 + (T)5 * s6 * w2 + e1 - f1 - (T)2 * e2 - (T)4 * f2;
+    g[4] = -s6 * w2 + e2 + f2;
+}
+
+// Transpose of the WENO5/LF b on one line, including the dependence of the
+// LF speed alpha = |nl| max|u| on u (its sub-gradient split over ties).
+// ubuf: the line u (logical base ub); gbuf: the cotangent of b (base gb).
+// Returns the result for the thread's own points 4c..4c+3 of its chunks
+// c = t + q*tpr in out[q][.].  Both buffers are overwritten (halo exchange).
+template <typename T>
+__device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, int M, int t, int tpr, bool active,
+                                                  T nlT, T mx, T eps, T dtau, T* redT, T out[8][4]) {
+    const int Nc = M >> 1;
+    const T alpha = (T)fabs(nlT) * mx;
+    const T idt = (T)1 / dtau;
+    T halo[8][5];
+    T abar = 0, nties = 0;
+    unsigned tie = 0, neg = 0;
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) out[q][i] = 0;
+        #pragma unroll
+        for (int i = 0; i < 5; ++i) halo[q][i] = 0;
+        if (active) {
+            quad<T> a = lds_quad(lds, ub, (c - 1) & (Nc - 1)), b = lds_quad(lds, ub, c),
+                    e = lds_quad(lds, ub, (c + 1) & (Nc - 1));
+            T u[12] = {a.v[0], a.v[1], a.v[2], a.v[3], b.v[0], b.v[1], b.v[2], b.v[3],
+                       e.v[0], e.v[1], e.v[2], e.v[3]};
+            quad<T> g0 = lds_quad(lds, gb, c), g1 = lds_quad(lds, gb, (c + 1) & (Nc - 1));
+            T gg[5] = {g0.v[0], g0.v[1], g0.v[2], g0.v[3], g1.v[0]};
+            T fp[12], fm[12], accP[12], accM[12];
+            #pragma unroll
+            for (int i = 0; i < 12; ++i) { accP[i] = 0; accM[i] = 0; }
+            #pragma unroll
+            for (int i = 2; i <= 10; ++i) {
+                T f = (T)0.5 * nlT * u[i] * u[i];
+                fp[i] = (T)0.5 * (f + alpha * u[i]);
+                fm[i] = (T)0.5 * (f - alpha * u[i]);
+            }
+            #pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                // face 4c+f+1/2: b_i has -F/dtau, b_{i+1} has +F/dtau
+                const T G = (gg[f + 1] - gg[f]) * idt;
+                T dp[5], dm[5];
+                weno_face_grad(fp[f + 2], fp[f + 3], fp[f + 4], fp[f + 5], fp[f + 6], eps, dp);
+                weno_face_grad(fm[f + 7], fm[f + 6], fm[f + 5], fm[f + 4], fm[f + 3], eps, dm);
+                #pragma unroll
+                for (int r = 0; r < 5; ++r) {
+                    accP[f + 2 + r] += G * dp[r];
+                    accM[f + 7 - r] += G * dm[r];
+                }
+            }
+            T contrib[12];
+            #pragma unroll
+            for (int i = 2; i <= 10; ++i) {
+                const T hu = (T)0.5 * u[i];
+                contrib[i] = accP[i] * ((T)0.5 * nlT * u[i] + (T)0.5 * alpha) +
+                             accM[i] * ((T)0.5 * nlT * u[i] - (T)0.5 * alpha);
+                abar += hu * (accP[i] - accM[i]);
+            }
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                out[q][i] = contrib[4 + i];
+                const T au = (T)fabs(u[4 + i]);
+                if (au == mx && mx > (T)0) {
+                    tie |= 1u << (4 * q + i);
+                    nties += (T)1;
+                }
+                if (u[4 + i] < (T)0) neg |= 1u << (4 * q + i);
+            }
+            halo[q][0] = contrib[2];
+            halo[q][1] = contrib[3];
+            halo[q][2] = contrib[8];
+            halo[q][3] = contrib[9];
+            halo[q][4] = contrib[10];
+        }
+    }
+    abar = line_sum(abar, tpr, redT);
+    nties = line_sum(nties, tpr, redT);
+    __syncthreads();
+    // halo exchange: left halo (points 4c-2, 4c-1) into the u buffer slots
+    // of chunk c; right halo (points 4c+4..4c+6) into the g buffer.
+    T* ur = reinterpret_cast<T*>(lds);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active) {
+            lds_quad_st(lds, ub, c, quad<T>{{halo[q][0], halo[q][1], (T)0, (T)0}});
+            lds_quad_st(lds, gb, c, quad<T>{{halo[q][2], halo[q][3], halo[q][4], (T)0}});
+        }
+    }
+    (void)ur;
+    __syncthreads();
+    const T aterm = nties > (T)0 ? abar * (T)fabs(nlT) / nties : (T)0;
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active) {
+            quad<T> lh = lds_quad(lds, ub, (c + 1) & (Nc - 1));   // chunk c+1's left halo: points 4c+2, 4c+3
+            quad<T> rh = lds_quad(lds, gb, (c - 1) & (Nc - 1));   // chunk c-1's right halo: points 4c..4c+2
+            out[q][0] += rh.v[0];
+            out[q][1] += rh.v[1];
+            out[q][2] += rh.v[2] + lh.v[0];
+            out[q][3] += lh.v[1];
+            #pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (tie & (1u << (4 * q + i))) out[q][i] += (neg & (1u << (4 * q + i))) ? -aterm : aterm;
+        }
+    }
+    __syncthreads();
+}
+
+// Adjoint tau-pass.  STAGE 1: cotangent T~1 (mixed spectrum) and u* ->
+// mu = J1^T t1 -> M~.  STAGE 2: T~2, R~ and u^n -> lam_n = r + J0^T t2 -> L~.
+// (The factor h is carried by the pre-scaled tables of the adjoint y-pass.)
+template <typename T, int STAGE>
+__global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __restrict__ descs,
+                                                              const TauItem* __restrict__ items,
+                                                              const cpx<T>* __restrict__ Tin,
+                                                              const cpx<T>* __restrict__ Rin,
+                                                              const T* __restrict__ ustore,
+                                                              cpx<T>* __restrict__ out,
+                                                              const cpx<T>* __restrict__ tw, int log2_ntw, int node,
+                                                              unsigned* __restrict__ status) {
+    __shared__ alignas(32) cpx<T> lds[2 * padded(TAU_THREADS * 16)];
+    __shared__ T redT[4];
+    __shared__ int redI[4];
+    const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstDesc& d = descs[it.inst];
+    const int M = d.M, N = 2 * M;
+    const int tpr = M >> 4;
+    const int r = threadIdx.x / tpr, t = threadIdx.x & (tpr - 1);
+    const int row = it.row0 + r;
+    const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
+    const int gb = r * M;                          // cotangent line
+    const int ub = TAU_THREADS * 16 + r * M;        // u line (second half of the buffer)
+    const int Nc = M >> 1;
+    const SpecIdx ix = {d.log2W, (long long)d.n_y << d.log2W};
+    const long long so = d.off_state + ((long long)row << d.log2W);
+
+    if (active) c2r_pre(Tin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    // the stored physical line
+    T mx = 0;
+    int bad = 0;
+    if (active) {
+        const quad<T>* ug = reinterpret_cast<const quad<T>*>(ustore + d.off_u + (long long)row * N);
+        for (int c = t; c < Nc; c += tpr) {
+            quad<T> v = ug[c];
+            #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bad |= !finite_val(v.v[i]);
+                mx = tmax(mx, (T)fabs(v.v[i]));
+            }
+            lds_quad_st(lds, ub, c, v);
+        }
+    }
+    __syncthreads();
+    lds_fft<T, 1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+    mx = line_max(mx, tpr, redT);
+    bad = line_or(bad, tpr, redI);
+    if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
+    const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
+    T res[8][4];
+    weno_adjoint_line(lds, ub, gb, M, t, tpr, active, (T)nl, mx, (T)d.weno_eps, (T)d.dtau, redT, res);
+    if (STAGE == 2) {
+        // lam_n = r + J0^T t2, with r the inverse tau-transform of R~
+        if (active) c2r_pre(Rin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+        __syncthreads();
+        lds_fft<T, 1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = t + q * tpr;
+            if (active) {
+                quad<T> v = lds_quad(lds, gb, c);
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) res[q][i] += v.v[i];
+            }
+        }
+        __syncthreads();
+    }
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = t + q * tpr;
+        if (active) lds_quad_st(lds, gb, c, quad<T>{{res[q][0], res[q][1], res[q][2], res[q][3]}});
+    }
+    __syncthreads();
+    lds_fft<T, -1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+    if (active) r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw);
+}
+
+// Adjoint y-pass.  STAGE 1: L~ -> Lh = F_y L~ (kept, tile-contiguous) and
+// T~1 = F_y^-1 conj(h Phi2) Z Lh.  STAGE 2: M~ and Lh ->
+// T~2 = F_y^-1 Z [conj(h(Phi1 - Phi2)) Lh + conj(h Phi1) Mh] and
+// R~ = F_y^-1 conj(E) (Lh + Mh).  Column 0 (DC, tau-Nyquist) pointwise in y;
+// its Lh slot holds the raw column.
+template <typename T, int NT, int STAGE>
+__global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ descs,
+                                                   const YItem* __restrict__ items, const cpx<T>* __restrict__ In,
+                                                   cpx<T>* __restrict__ Lh, cpx<T>* __restrict__ Tout,
+                                                   cpx<T>* __restrict__ Rout, const cpx<T>* __restrict__ tabs,
+                                                   const cpx<T>* __restrict__ tw, int log2_ntw) {
+    __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
+    const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const InstDesc& d = descs[it.inst];
+    const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
+    const int m0 = it.m0;
+    const int tid = threadIdx.x;
+    const int nthr = W * (Ny >> 4);
+    const bool act = tid < nthr;
+    const int c = tid & (W - 1), t = tid >> lw;
+    const int ne = W * Ny;
+    const long long to = d.off_state + (long long)m0 * Ny;
+    const cpx<T>* It = In + to;
+    cpx<T>* Lt = Lh + to;
+    cpx<T>* Tt = Tout + to;
+    const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
+    const cpx<T>* tP1 = tE + d.tab_stride;
+    const cpx<T>* tP2 = tE + 2 * d.tab_stride;
+    const bool col0 = (m0 == 0);
+    const int half = Ny >> 1;
+
+    for (int e = tid; e < ne; e += NT) lds[padi(e)] = It[e];
+    __syncthreads();
+    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    cpx<T> keep[16];
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * NT;
+        if (e < ne) {
+            const int j = e >> lw, cc = e & (W - 1);
+            const int n = j <= half ? j : Ny - j;
+            const int ti = n * W + cc;
+            cpx<T> X = lds[padi(e)];
+            if (STAGE == 1) {
+                if (!(col0 && cc == 0)) Lt[e] = X;
+                lds[padi(e)] = cmulc(X, tP2[ti]);
+            } else {
+                cpx<T> L = Lt[e];
+                cpx<T> p1 = tP1[ti], p2 = tP2[ti];
+                lds[padi(e)] = cmulc(L, p1 - p2) + cmulc(X, p1);
+                keep[q] = cmulc(L + X, tE[ti]);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    for (int e = tid; e < ne; e += NT) {
+        if (!(col0 && (e & (W - 1)) == 0)) Tt[e] = lds[padi(e)];
+    }
+    if (STAGE == 2) {
+        __syncthreads();
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + q * NT;
+            if (e < ne) lds[padi(e)] = keep[q];
+        }
+        __syncthreads();
+        lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+        cpx<T>* Rt = Rout + to;
+        for (int e = tid; e < ne; e += NT) {
+            if (!(col0 && (e & (W - 1)) == 0)) Rt[e] = lds[padi(e)];
+        }
+    }
+    if (col0) {
+        const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
+        for (int y = tid; y < Ny; y += NT) {
+            const long long o = (long long)y * W;
+            if (STAGE == 1) {
+                const cpx<T> l = It[o];
+                Lt[o] = l;
+                Tt[o] = cpx<T>{(T)0, P2N * l.y};
+            } else {
+                const cpx<T> l = Lt[o], m = It[o];
+                Tt[o] = cpx<T>{(T)0, (P1N - P2N) * l.y + P1N * m.y};
+                Rout[to + o] = cpx<T>{l.x + m.x, EN * (l.y + m.y)};
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ multiplier tables
 // phi-functions in FP64: Taylor series of phi2 (Horner) for |z| < 1, with
 // phi1 = 1 + z phi2 and e^z = 1 + z phi1; closed forms otherwise.
@@ -507,6 +846,7 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
     case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
     case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
     case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
+    case 3: hipLaunchKernelGGL((tau_kernel<T, 3>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -557,6 +897,65 @@ hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* ta
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
+                          const void* Rin, const T* ustore, void* out, const void* tw, int log2_ntw, int node,
+                          unsigned* status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    dim3 g(n_items), b(TAU_THREADS);
+    const cpx<T>* ti = static_cast<const cpx<T>*>(Tin);
+    const cpx<T>* ri = static_cast<const cpx<T>*>(Rin);
+    cpx<T>* o = static_cast<cpx<T>*>(out);
+    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    if (stage == 1)
+        hipLaunchKernelGGL((tau_adj_kernel<T, 1>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, log2_ntw, node, status);
+    else
+        hipLaunchKernelGGL((tau_adj_kernel<T, 2>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, log2_ntw, node, status);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
+                                  void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
+                                  hipStream_t s) {
+    dim3 g(n_items), b(NT);
+    const cpx<T>* in = static_cast<const cpx<T>*>(In);
+    cpx<T>* lh = static_cast<cpx<T>*>(Lh);
+    cpx<T>* to = static_cast<cpx<T>*>(Tout);
+    cpx<T>* ro = static_cast<cpx<T>*>(Rout);
+    const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
+    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    if (stage == 1)
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, w, log2_ntw);
+    else
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, w, log2_ntw);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
+                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
+                        hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (nt) {
+    case 256: return launch_y_adj_nt<T, 256>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
+    case 512: return launch_y_adj_nt<T, 512>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
+    case 1024:
+        if constexpr (sizeof(T) == 4)
+            return launch_y_adj_nt<T, 1024>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_tau_adj<float>(int, const InstDesc*, const TauItem*, int, const void*, const void*,
+                                          const float*, void*, const void*, int, int, unsigned*, hipStream_t);
+template hipError_t launch_tau_adj<double>(int, const InstDesc*, const TauItem*, int, const void*, const void*,
+                                           const double*, void*, const void*, int, int, unsigned*, hipStream_t);
+template hipError_t launch_y_adj<float>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,
+                                        void*, const void*, const void*, int, hipStream_t);
+template hipError_t launch_y_adj<double>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,
+                                         void*, const void*, const void*, int, hipStream_t);
 template hipError_t launch_tau<float>(int, const InstDesc*, const TauItem*, int, const float*, float*, const void*,
                                       void*, const void*, int, int, int, unsigned*, hipStream_t);
 template hipError_t launch_tau<double>(int, const InstDesc*, const TauItem*, int, const double*, double*,
