@@ -119,6 +119,13 @@ kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
  * only); rebuilds the tiled multiplier tables.  0 restores the default. */
 kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
+/* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is
+ * read, never written) for every supported y-pass block size, keep the
+ * fastest and return it (> 0), or return -(kzk_status) on error.  The
+ * y-pass block size fixes the column-tile width W = threads * 16 / n_y of
+ * the y-FFTs (and so the radix-16 Stockham work per block).  Synchronises. */
+int32_t kzk_autotune(kzk_plan *plan, const void *u_dev, int32_t n_trial);
+
 /* Current y-pass block size. */
 int32_t kzk_get_y_threads(const kzk_plan *plan);
 

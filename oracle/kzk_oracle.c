@@ -146,7 +146,8 @@ void orc_phi(int k, double zr, double zi, double *out_r, double *out_i)
 
 static double wavenumber(int idx, int npts, double len)
 {
-    int s = idx < npts / 2 ? idx : idx - npts;   /* signed index */
+    /* signed index; a length-1 transform has the single wavenumber 0 */
+    int s = (npts == 1 || idx < npts / 2) ? idx : idx - npts;
     return 2.0 * PI * (double)s / len;
 }
 

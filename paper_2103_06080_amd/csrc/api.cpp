@@ -566,6 +566,42 @@ kzk_status adjoint_workspace(kzk_plan* p, size_t ckpt, size_t nseg) {
 
 }  // namespace
 
+extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
+    if (!p || !u || n_trial < 1) return -(int32_t)KZK_ERR_ARG;
+    if (p->steps_limit >= 0 && n_trial > p->steps_limit) n_trial = (int32_t)p->steps_limit;
+    if (n_trial < 1) return -(int32_t)KZK_ERR_STATE;
+    const int cands[3] = {1024, 512, 256};
+    int best = p->y_threads;
+    float best_ms = 1e30f;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -(int32_t)KZK_ERR_DEVICE;
+    const bool prof = p->prof;
+    p->prof = false;
+    kzk_status st = KZK_OK;
+    for (int c : cands) {
+        if (!kzk::y_threads_supported(p->dtype == KZK_F64, c)) continue;
+        if ((st = kzk_set_y_threads(p, c)) != KZK_OK) break;
+        // one untimed step to warm up, then n_trial timed steps, on the plan's own state
+        if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+        if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
+        if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+        (void)hipEventRecord(a, p->stream);
+        if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
+        (void)hipEventRecord(b, p->stream);
+        if (hipEventSynchronize(b) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    p->prof = prof;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipMemset(p->dStatus, 0, sizeof(unsigned));   // trial steps ran on scratch state
+    if (st != KZK_OK) return -(int32_t)st;
+    if ((st = kzk_set_y_threads(p, best)) != KZK_OK) return -(int32_t)st;
+    return best;
+}
+
 extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;

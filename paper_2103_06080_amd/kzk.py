@@ -22,7 +22,7 @@ STATUS = {0: "KZK_OK", 1: "KZK_ERR_ARG", 2: "KZK_ERR_SIZE", 3: "KZK_ERR_OOM", 4:
 EXPORTS = ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_inst_offset", "kzk_set_stream",
            "kzk_set_graph", "kzk_set_y_threads", "kzk_get_y_threads", "kzk_destroy", "kzk_status_str",
            "kzk_eval_b", "kzk_tau_forward", "kzk_tau_inverse", "kzk_profile_enable", "kzk_profile_read",
-           "kzk_read_tables"]
+           "kzk_read_tables", "kzk_autotune"]
 KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "other"]
 
 
@@ -81,6 +81,8 @@ def lib():
         L.kzk_profile_enable.argtypes = [vp, i32]
         L.kzk_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i32]
         L.kzk_read_tables.argtypes = [vp, i32, vp]
+        L.kzk_autotune.argtypes = [vp, vp, i32]
+        L.kzk_autotune.restype = i32
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -220,6 +222,14 @@ class Plan:
         cnt = (ctypes.c_int32 * n)()
         _check(lib().kzk_profile_read(self.h, ms, cnt, n), "kzk_profile_read")
         return {KINDS[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    def autotune(self, u, n_trial: int = 3) -> int:
+        """Pick the fastest y-pass block size on this plan (u is only read)."""
+        self._check_field(u)
+        r = lib().kzk_autotune(self.h, ctypes.c_void_p(u.data_ptr()), int(n_trial))
+        if r < 0:
+            raise KZKError(-r, "kzk_autotune")
+        return r
 
     def read_tables(self, inst: int = 0):
         """(E/n_y, h Phi1/n_y, h Phi2/n_y) as complex numpy arrays [n_tau/2, n_y/2+1]."""

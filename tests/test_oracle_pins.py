@@ -350,6 +350,20 @@ def test_y_independent_field_stays_y_independent(orc):
     assert np.abs(u - u[0:1]).max() < 1e-14
 
 
+def test_single_row_grid_equals_y_independent_field(orc):
+    """A y-independent field stays y-independent and its rows do not feel the
+    diffraction term (ky = 0 only): the march on a one-row grid must equal
+    every row of the march on a many-row grid."""
+    p = small_problem(nt=128, ny=8, h=2e-3, n_steps=25, D=0.05, nl=1.0, A=1e-3)
+    row = I.random_field(10, (1, 128)) + 0.2 * np.sin(2 * np.pi * p.tau() / 8)[None, :]
+    p.u0 = np.tile(row, (8, 1))
+    many = orc.run(p)
+    q = small_problem(nt=128, ny=1, h=2e-3, n_steps=25, D=0.05, nl=1.0, A=1e-3)
+    q.u0 = row.copy()
+    one = orc.run(q)
+    assert np.abs(many - one).max() < 1e-14
+
+
 def test_odd_symmetry_preserved_without_diffraction(orc):
     p = small_problem(nt=128, ny=2, h=2e-3, n_steps=50, D=0.0, nl=1.0)
     tau = p.tau()
