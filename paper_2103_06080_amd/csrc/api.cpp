@@ -42,7 +42,7 @@ struct kzk_plan {
     bool any_D_sched = false;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
-    void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dTab = nullptr, *dTw = nullptr;
+    void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dU = nullptr, *dTab = nullptr, *dTw = nullptr;
     InstDesc* dDesc = nullptr;
     TauItem* dTau = nullptr;
     YItem* dY = nullptr;
@@ -181,15 +181,15 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
 }
 
 hipError_t ypass(kzk_plan* p, int stage) {
-    ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : KZK_KIND_Y2);
+    ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP,
-                                    p->dTab, p->dTw, p->log2_ntw, p->stream);
-    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP, p->dTab,
-                                 p->dTw, p->log2_ntw, p->stream);
+                                    p->dU, p->dTab, p->dTw, p->log2_ntw, p->stream);
+    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP, p->dU,
+                                 p->dTab, p->dTw, p->log2_ntw, p->stream);
 }
 
-// Steps s .. s+n-1 on the spectral state dC (no transforms at the ends).
+// Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
 kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
     for (int s = first; s < first + n; ++s) {
         if (p->any_D_sched) {
@@ -222,8 +222,15 @@ hipError_t y_adj(kzk_plan* p, int stage, const void* In, void* Lh, void* Tout, v
                                      p->dTw, p->log2_ntw, p->stream);
 }
 
-kzk_status enqueue_march(kzk_plan* p, void* u, int first, int n) {
+// u -> state: tau-spectrum per row (dC), then the full spectrum (dU).
+kzk_status enqueue_forward(kzk_plan* p, const void* u) {
     if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    if (ypass(p, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+
+kzk_status enqueue_march(kzk_plan* p, void* u, int first, int n) {
+    if (enqueue_forward(p, u) != KZK_OK) return KZK_ERR_DEVICE;
     kzk_status st = enqueue_steps(p, first, n);
     if (st != KZK_OK) return st;
     if (tau(p, 1, nullptr, u, p->dC, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
@@ -338,7 +345,8 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
     const size_t cz = 2 * p->esz;   // bytes per complex
     kzk_status st = KZK_OK;
     if ((st = dev_alloc(p, &p->dC, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dB, so * cz)) != KZK_OK ||
-        (st = dev_alloc(p, &p->dP, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dTab, 3 * to * cz)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dP, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dU, so * cz)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dTab, 3 * to * cz)) != KZK_OK ||
         (st = dev_alloc(p, &p->dTw, (size_t)ntw * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dDesc, sizeof(InstDesc) * n_inst)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dTau, sizeof(TauItem) * max_tau_items)) != KZK_OK ||
@@ -557,7 +565,7 @@ kzk_status adjoint_workspace(kzk_plan* p, size_t ckpt, size_t nseg) {
         p->adj_ckpt_cap = ckpt;
     }
     if (nseg > p->adj_seg_cap) {
-        kzk_status st = dev_alloc(p, &p->dCk, nseg * sb);
+        kzk_status st = dev_alloc(p, &p->dCk, 2 * nseg * sb);
         if (st != KZK_OK) return st;
         p->adj_seg_cap = nseg;
     }
@@ -582,9 +590,9 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
         if (!kzk::y_threads_supported(p->dtype == KZK_F64, c)) continue;
         if ((st = kzk_set_y_threads(p, c)) != KZK_OK) break;
         // one untimed step to warm up, then n_trial timed steps, on the plan's own state
-        if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+        if ((st = enqueue_forward(p, u)) != KZK_OK) break;
         if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
-        if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+        if ((st = enqueue_forward(p, u)) != KZK_OK) break;
         (void)hipEventRecord(a, p->stream);
         if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
         (void)hipEventRecord(b, p->stream);
@@ -621,10 +629,11 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
     char* Us = (char*)p->dUs;
 
     // forward sweep, keeping the spectral state at the start of every segment
-    if (tau(p, 0, u0, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    if ((st = enqueue_forward(p, u0)) != KZK_OK) return st;
     for (int g = 0; g < nseg; ++g) {
         const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
-        if (hipMemcpyAsync(ck + (size_t)g * sb, p->dC, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+        if (hipMemcpyAsync(ck + (size_t)(2 * g) * sb, p->dU, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess ||
+            hipMemcpyAsync(ck + (size_t)(2 * g + 1) * sb, p->dC, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
             return KZK_ERR_DEVICE;
         if ((st = enqueue_steps(p, s0, s1 - s0)) != KZK_OK) return st;
     }
@@ -632,7 +641,8 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
     if (tau(p, 0, lam, nullptr, nullptr, p->dL, 0) != hipSuccess) return KZK_ERR_DEVICE;
     for (int g = nseg - 1; g >= 0; --g) {
         const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
-        if (hipMemcpyAsync(p->dC, ck + (size_t)g * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+        if (hipMemcpyAsync(p->dU, ck + (size_t)(2 * g) * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess ||
+            hipMemcpyAsync(p->dC, ck + (size_t)(2 * g + 1) * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
             return KZK_ERR_DEVICE;
         // recompute the segment, storing u^n and u* in physical space
         for (int s = s0; s < s1; ++s) {

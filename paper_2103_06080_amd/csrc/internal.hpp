@@ -44,7 +44,7 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    void* C, const void* B, void* P, const void* tabs, const void* tw, int log2_ntw,
+                    void* C, const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw,
                     hipStream_t s);
 
 template <typename T>

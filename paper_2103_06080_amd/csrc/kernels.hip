@@ -1,15 +1,16 @@
 // kernels.hip -- HIP kernels of the exponential-integrator/WENO5 step (gfx950).
 //
-// State between steps: C~(m, y), the tau-spectrum of u for every y-row
-// (y physical), packed R2C layout: M = n_tau/2 complex per row, slot 0 holds
-// the real DC mode in .x and the real tau-Nyquist mode in .y.
+// Spectra are packed R2C along tau: M = n_tau/2 complex per row, slot 0
+// holds the real DC mode in .x and the real tau-Nyquist mode in .y.
 //
-// One ExpRK22 step (Sec. 3.4 eq. (20), Algorithm 2) is four kernels:
+// The state between steps is the full spectrum U = F(u) (as in Algorithm 2),
+// with its tau-spectrum per y-row C~ (y physical) alongside for the next
+// tau-pass.  One ExpRK22 step (Sec. 3.4 eq. (20), Algorithm 2) is four kernels:
 //   tau-pass (node x_n)      C~  -> inverse tau-FFT -> u^n -> LF speed ->
 //                                    WENO5 b -> forward tau-FFT -> B~
-//   y-pass stage 1           y-FFT of B~ and C~, E/Phi1/Phi2 combine:
+//   y-pass stage 1           y-FFT of B~, E/Phi1/Phi2 combine with U:
 //                                    U* = E U + h Phi1 B,  P = E U + h (Phi1-Phi2) B,
-//                                    inverse y-FFT of U* -> C~ (in place), P kept
+//                                    inverse y-FFT of U* -> C~*, P kept
 //   tau-pass (node x_{n+1})  C~* -> B~*
 //   y-pass stage 2           U^{n+1} = P + h Phi2 B*, inverse y-FFT -> C~
 // Column 0 (DC and tau-Nyquist) needs no y-FFT: the DC multipliers are
@@ -325,16 +326,28 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 
 // ------------------------------------------------------------------ y-pass
 // A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows.
-// The spectra C~, B~ are stored in column tiles [m / W][y][m % W], so the
-// tile is one contiguous block of W * n_y values, staged in LDS in the same
-// order (lds[y * W + c]); W * n_y / 16 threads run the y-FFTs.
-// The multiplier tables are stored per tile as tab[m0 * Nh + n * W + c]
-// (n = |ky index|, the symbol is even in ky), pre-scaled by 1/n_y for the
-// inverse y-transform.  P is stored tile-contiguously at P[m0 * n_y + e].
+// The mixed spectra C~, B~ (tau-spectral, y-physical) are stored in column
+// tiles [m / W][y][m % W], so the tile is one contiguous block of W * n_y
+// values, staged in LDS in the same order (lds[y * W + c]); W * n_y / 16
+// threads run the y-FFTs.  The fully spectral state U and the stage value P
+// are stored tile-contiguously at [m0 * n_y + e] in the same element order
+// (e = y-wavenumber index * W + c).  The multiplier tables are stored per
+// tile as tab[m0 * Nh + n * W + c] (n = |ky index|, the symbol is even in
+// ky), pre-scaled by 1/n_y for the inverse y-transform.
+//
+// STAGE 0: U = F_y C~                           (start of a march)
+// STAGE 1: U* = E U + h Phi1 F_y B~,  P = E U + h (Phi1 - Phi2) F_y B~,
+//          C~* = F_y^-1 U*
+// STAGE 2: U^{n+1} = P + h Phi2 F_y B~*,  C~^{n+1} = F_y^-1 U^{n+1}
+// (F_y unnormalised; U is kept unnormalised, P and the inputs of the inverse
+// transform carry the factor 1/n_y of the pre-scaled tables.)
+// Column 0 holds the DC (.x) and tau-Nyquist (.y) modes in y-physical form in
+// every array; its DC is invariant and its Nyquist multipliers are scalars.
 template <typename T, int NT, int STAGE>
 __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
                                                cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
-                                               cpx<T>* __restrict__ P, const cpx<T>* __restrict__ tabs,
+                                               cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
+                                               const cpx<T>* __restrict__ tabs,
                                                const cpx<T>* __restrict__ tw, int log2_ntw) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
@@ -346,82 +359,72 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     const bool act = tid < nthr;
     const int c = tid & (W - 1), t = tid >> lw;
     const int ne = W * Ny;
-    const long long so = d.off_state;
-    const cpx<T>* Bt = B + so + (long long)m0 * Ny;
-    cpx<T>* Ct = C + so + (long long)m0 * Ny;
-    cpx<T>* Pt = P + so + (long long)m0 * Ny;
+    const long long to = d.off_state + (long long)m0 * Ny;
+    const cpx<T>* Bt = B + to;
+    cpx<T>* Ct = C + to;
+    cpx<T>* Pt = P + to;
+    cpx<T>* Ut = U + to;
     const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
     const cpx<T>* tP1 = tE + d.tab_stride;
     const cpx<T>* tP2 = tE + 2 * d.tab_stride;
     const bool col0 = (m0 == 0);
     const int half = Ny >> 1;
 
-    for (int e = tid; e < ne; e += NT) lds[padi(e)] = Bt[e];
-    __syncthreads();
-    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
-
-    if (STAGE == 1) {
-        cpx<T> bh[16];
-        #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = tid + q * NT;
-            if (e < ne) bh[q] = lds[padi(e)];
-        }
-        __syncthreads();
+    if (STAGE == 0) {
         for (int e = tid; e < ne; e += NT) lds[padi(e)] = Ct[e];
         __syncthreads();
         lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
-        #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = tid + q * NT;
-            if (e < ne) {
-                const int j = e >> lw, cc = e & (W - 1);
-                const int n = j <= half ? j : Ny - j;
-                const int ti = n * W + cc;
-                cpx<T> E = tE[ti], p1 = tP1[ti], p2 = tP2[ti];
-                cpx<T> U = lds[padi(e)];
-                cpx<T> EU = cmul(E, U);
-                cpx<T> Us = EU + cmul(p1, bh[q]);
-                cpx<T> Pv = EU + cmul(p1 - p2, bh[q]);
-                if (!(col0 && cc == 0)) Pt[e] = Pv;
-                lds[padi(e)] = Us;
-            }
-        }
-        __syncthreads();
-    } else {
-        #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = tid + q * NT;
-            if (e < ne) {
-                const int j = e >> lw, cc = e & (W - 1);
-                const int n = j <= half ? j : Ny - j;
-                lds[padi(e)] = Pt[e] + cmul(tP2[n * W + cc], lds[padi(e)]);
-            }
-        }
-        __syncthreads();
+        for (int e = tid; e < ne; e += NT)
+            Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[padi(e)];
+        return;
     }
+
+    for (int e = tid; e < ne; e += NT) lds[padi(e)] = Bt[e];
+    __syncthreads();
+    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    #pragma unroll 4
+    for (int e = tid; e < ne; e += NT) {
+        const int j = e >> lw, cc = e & (W - 1);
+        const int n = j <= half ? j : Ny - j;
+        const int ti = n * W + cc;
+        const cpx<T> bh = lds[padi(e)];
+        if (STAGE == 1) {
+            const cpx<T> EU = cmul(tE[ti], Ut[e]);
+            const cpx<T> p1 = tP1[ti], p2 = tP2[ti];
+            if (!(col0 && cc == 0)) Pt[e] = EU + cmul(p1 - p2, bh);
+            lds[padi(e)] = EU + cmul(p1, bh);
+        } else {
+            // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
+            // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
+            const cpx<T> un = Pt[e] + cmul(tP2[ti], bh);
+            if (!(col0 && cc == 0)) Ut[e] = (T)Ny * un;
+            lds[padi(e)] = un;
+        }
+    }
+    __syncthreads();
     lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
     for (int e = tid; e < ne; e += NT) {
-        const int cc = e & (W - 1);
-        if (!(col0 && cc == 0)) Ct[e] = lds[padi(e)];
+        if (!(col0 && (e & (W - 1)) == 0)) Ct[e] = lds[padi(e)];
     }
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
         const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
         for (int y = tid; y < Ny; y += NT) {
-            const cpx<T> b = Bt[(long long)y * W];
+            const long long o = (long long)y * W;
+            const cpx<T> b = Bt[o];
             if (STAGE == 1) {
-                const cpx<T> cr = Ct[(long long)y * W];
-                Ct[(long long)y * W] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
-                Pt[(long long)y * W] = cpx<T>{cr.x, EN * cr.y + (P1N - P2N) * b.y};
+                const cpx<T> cr = Ut[o];
+                Ct[o] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
+                Pt[o] = cpx<T>{cr.x, EN * cr.y + (P1N - P2N) * b.y};
             } else {
-                const cpx<T> p = Pt[(long long)y * W];
-                Ct[(long long)y * W] = cpx<T>{p.x, p.y + P2N * b.y};
+                const cpx<T> p = Pt[o];
+                const cpx<T> un = cpx<T>{p.x, p.y + P2N * b.y};
+                Ct[o] = un;
+                Ut[o] = un;
             }
         }
     }
 }
-
 
 // ------------------------------------------------------------------ adjoint
 // Transpose of the step map u^n -> u^{n+1} (ExpRK22, Sec. 3.3 eq. (19)) on
@@ -854,18 +857,21 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 
 template <typename T, int NT>
 static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                              const void* B, void* P, const void* tabs, const void* tw, int log2_ntw,
+                              const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw,
                               hipStream_t s) {
     dim3 g(n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
     cpx<T>* p = static_cast<cpx<T>*>(P);
+    cpx<T>* u = static_cast<cpx<T>*>(U);
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
-    if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, tb, w, log2_ntw);
+    if (stage == 0)
+        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
+    else if (stage == 1)
+        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
     return hipGetLastError();
 }
 
@@ -876,14 +882,14 @@ bool y_threads_supported(int is_f64, int nt) {
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                    const void* B, void* P, const void* tabs, const void* tw, int log2_ntw, hipStream_t s) {
+                    const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (nt) {
-    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
-    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
+    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
+    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, tabs, tw, log2_ntw, s);
+            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -960,9 +966,9 @@ template hipError_t launch_tau<float>(int, const InstDesc*, const TauItem*, int,
                                       void*, const void*, int, int, int, unsigned*, hipStream_t);
 template hipError_t launch_tau<double>(int, const InstDesc*, const TauItem*, int, const double*, double*,
                                        const void*, void*, const void*, int, int, int, unsigned*, hipStream_t);
-template hipError_t launch_y<float>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
+template hipError_t launch_y<float>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*,
                                     const void*, const void*, int, hipStream_t);
-template hipError_t launch_y<double>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*,
+template hipError_t launch_y<double>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*,
                                      const void*, const void*, int, hipStream_t);
 template hipError_t launch_tables<float>(const InstDesc*, int, int, void*, int, hipStream_t);
 template hipError_t launch_tables<double>(const InstDesc*, int, int, void*, int, hipStream_t);
