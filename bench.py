@@ -43,12 +43,13 @@ def kernel_model(kind, n_tau, n_y, esz):
         # read C~, write B~; two real tau-FFTs (2.5 N log2 N each) + WENO5 (~120 flops/point)
         return 2 * arr, N * (5.0 * lg + 120.0)
     if kind == "y_pass1":
-        # read B~, C~; write P, C~*; three complex y-FFTs of N/2 points + combine
+        # read B~, U; write P, C~*; two complex y-FFTs of N/2 points + combine
         lgy = (n_y.bit_length() - 1)
-        return 4 * arr, N * (3 * 2.5 * lgy + 12.0)
+        return 4 * arr, N * (2 * 2.5 * lgy + 12.0)
     if kind == "y_pass2":
+        # read B~*, P; write U, C~
         lgy = (n_y.bit_length() - 1)
-        return 3 * arr, N * (2 * 2.5 * lgy + 4.0)
+        return 4 * arr, N * (2 * 2.5 * lgy + 4.0)
     return None, None
 
 
@@ -174,8 +175,8 @@ def main():
         roofline["algorithmic_flops_per_launch"] = nflops
         roofline["hbm_gbs_algorithmic"] = round(gbs, 1)
         roofline["traffic"] = pmc_traffic(dom, args.config, args.dtype)
-        # whole-step model: 11 array transfers per ExpRK22 step
-        roofline["step_model_gbs"] = round(11 * esz * prob.points * steps_per_march * args.steps / elapsed / 1e9, 1)
+        # whole-step model: 12 array transfers per ExpRK22 step
+        roofline["step_model_gbs"] = round(12 * esz * prob.points * steps_per_march * args.steps / elapsed / 1e9, 1)
 
     cpu = None
     if not args.no_cpu_baseline:
