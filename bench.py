@@ -82,6 +82,66 @@ def cpu_baseline(problem):
                       "and final 2D transforms), %.1f s" % (problem.n_tau, problem.n_y, dt)}
 
 
+def _time(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def side_measurements(args, value_fp32, ms_fp32):
+    """FP64 march of the same workload, the adjoint/forward time ratio on the
+    2048 x 1024 adjoint workload, and the batched 64-solve throughput."""
+    import torch
+    from paper_2103_06080_amd import autograd, inputs, kzk
+    sync = torch.cuda.synchronize
+    out = {}
+    # FP64, same march
+    p = inputs.c3(n_steps=2 * 2000)
+    plan = kzk.Plan(p, dtype="f64")
+    u = plan.pack([p.u0])
+    plan.step(u, 0, 2000)
+    t = _time(lambda: plan.step(u, 2000, 2000), sync)
+    assert plan.poll() == 0
+    v64 = p.points * 2000 / t
+    out["fp64_c3"] = {"s_per_march": t, "value": v64, "fp32_speedup": value_fp32 / v64}
+    del plan, u
+    torch.cuda.empty_cache()
+    # adjoint / forward on the adjoint workload (FP32 and FP64)
+    q = inputs.c5()
+    for dt in ("f32", "f64"):
+        plan = kzk.Plan(q, dtype=dt)
+        u0 = plan.pack([q.u0])
+        u = u0.clone()
+        plan.step(u, 0, q.n_steps)
+        u.copy_(u0)
+        tf = _time(lambda: plan.step(u, 0, q.n_steps), sync)
+        lam = torch.ones_like(u0)
+        plan.adjoint(u0, lam, 0, q.n_steps, inputs.C5_CKPT)
+        ta = _time(lambda: plan.adjoint(u0, lam, 0, q.n_steps, inputs.C5_CKPT), sync)
+        assert plan.poll() == 0
+        out["adjoint_c5_" + dt] = {"fwd_s": tf, "adjoint_s": ta, "adjoint_over_fwd": ta / tf,
+                                   "ckpt_every": inputs.C5_CKPT}
+        del plan
+    torch.cuda.empty_cache()
+    # batched: 64 uneven solves in one plan, the whole march replayed as one HIP graph
+    probs = inputs.c4()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = kzk.Plan(probs, dtype="f32", stream=stream, graph=True)
+        u = plan.pack([pp.u0 for pp in probs])
+        u0 = u.clone()
+        plan.step(u, 0, 500)
+        u.copy_(u0)
+        tb = _time(lambda: plan.step(u, 0, 500), stream.synchronize)
+        assert plan.poll() == 0
+    pts = sum(pp.points for pp in probs)
+    out["batched_c4_f32"] = {"solves": len(probs), "points": pts, "s_per_march": tb,
+                             "value": pts * 500 / tb, "graph": True, "y_threads": plan.y_threads}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +155,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for memory counters)")
     ap.add_argument("--march-steps", type=int, default=0, help="override the steps of one march (profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64, adjoint and batched side measurements")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -178,6 +240,13 @@ def main():
         # whole-step model: 12 array transfers per ExpRK22 step
         roofline["step_model_gbs"] = round(12 * esz * prob.points * steps_per_march * args.steps / elapsed / 1e9, 1)
 
+    y_threads = plan.y_threads
+    extras = None
+    if not args.no_extras and args.config == "c3" and not args.march_steps:
+        del plan, u
+        torch.cuda.empty_cache()
+        extras = side_measurements(args, value, ms_per_step)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(base)
@@ -197,9 +266,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s, %s" % (args.config, WORKLOADS[args.config], args.dtype),
                    "n_tau": prob.n_tau, "n_y": prob.n_y, "march_steps": steps_per_march,
-                   "y_threads": plan.y_threads, "parallelism": "single GPU"},
+                   "y_threads": y_threads, "parallelism": "single GPU"},
         "roofline": roofline,
         "kernels": kernels,
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -121,9 +121,10 @@ kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
 /* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is
  * read, never written) for every supported y-pass block size, keep the
- * fastest and return it (> 0), or return -(kzk_status) on error.  The
- * y-pass block size fixes the column-tile width W = threads * 16 / n_y of
- * the y-FFTs (and so the radix-16 Stockham work per block).  Synchronises. */
+ * fastest and return it (> 0), or return -(kzk_status) on error.  The y-pass
+ * block size fixes the column-tile width W = threads * 16 / n_y of the
+ * y-FFTs and of the spectral layout (and so the row segments of the
+ * tau-pass).  Synchronises. */
 int32_t kzk_autotune(kzk_plan *plan, const void *u_dev, int32_t n_trial);
 
 /* Current y-pass block size. */

@@ -44,9 +44,10 @@ struct kzk_plan {
 
     void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dU = nullptr, *dTab = nullptr, *dTw = nullptr;
     InstDesc* dDesc = nullptr;
-    TauItem* dTau = nullptr;
+    TauItem* dTau = nullptr;    // tau-pass work list (TAU_THREADS * 16 / M lines per item)
     YItem* dY = nullptr;
-    int n_tau_items = 0, n_y_items = 0;
+    int n_tau_items = 0, n_y_items = 0, max_tau_items = 0;
+    void* dTwSt = nullptr;      // per-stage Stockham twiddles
     unsigned* dStatus = nullptr;
     double* dSched = nullptr;
     std::vector<void*> owned;             // everything hipMalloc'ed, freed in destroy
@@ -144,7 +145,7 @@ kzk_status layout(kzk_plan* p) {
         for (int m = 0; m < d.M; m += W) ys.push_back({i, m});
     }
     // the item arrays are sized for the largest case at create (W >= 1)
-    if ((int)tau.size() > p->n_tau_items && p->dTau) return KZK_ERR_STATE;
+    if ((int)tau.size() > p->max_tau_items) return KZK_ERR_STATE;
     p->n_tau_items = (int)tau.size();
     p->n_y_items = (int)ys.size();
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
@@ -175,18 +176,18 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
     ProfScope ps(p, mode == 2 ? KZK_KIND_TAU : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_tau<float>(mode, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in, (float*)u_out,
-                                      Cin, Bout, p->dTw, p->log2_ntw, node, tiled, p->dStatus, p->stream);
+                                      Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->dStatus, p->stream);
     return kzk::launch_tau<double>(mode, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in, (double*)u_out,
-                                   Cin, Bout, p->dTw, p->log2_ntw, node, tiled, p->dStatus, p->stream);
+                                   Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->dStatus, p->stream);
 }
 
 hipError_t ypass(kzk_plan* p, int stage) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP,
-                                    p->dU, p->dTab, p->dTw, p->log2_ntw, p->stream);
+                                    p->dU, p->dTab, p->dTwSt, p->stream);
     return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP, p->dU,
-                                 p->dTab, p->dTw, p->log2_ntw, p->stream);
+                                 p->dTab, p->dTwSt, p->stream);
 }
 
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
@@ -208,18 +209,18 @@ hipError_t tau_adj(kzk_plan* p, int stage, const void* Tin, const void* Rin, con
     ProfScope ps(p, KZK_KIND_ADJ_TAU);
     if (p->dtype == KZK_F32)
         return kzk::launch_tau_adj<float>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const float*)ustore, out,
-                                          p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+                                          p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus, p->stream);
     return kzk::launch_tau_adj<double>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const double*)ustore, out,
-                                       p->dTw, p->log2_ntw, node, p->dStatus, p->stream);
+                                       p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus, p->stream);
 }
 
 hipError_t y_adj(kzk_plan* p, int stage, const void* In, void* Lh, void* Tout, void* Rout) {
     ProfScope ps(p, KZK_KIND_ADJ_Y);
     if (p->dtype == KZK_F32)
         return kzk::launch_y_adj<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout,
-                                        p->dTab, p->dTw, p->log2_ntw, p->stream);
+                                        p->dTab, p->dTwSt, p->stream);
     return kzk::launch_y_adj<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout, p->dTab,
-                                     p->dTw, p->log2_ntw, p->stream);
+                                     p->dTwSt, p->stream);
 }
 
 // u -> state: tau-spectrum per row (dC), then the full spectrum (dU).
@@ -350,13 +351,14 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
         (st = dev_alloc(p, &p->dTw, (size_t)ntw * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dDesc, sizeof(InstDesc) * n_inst)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dTau, sizeof(TauItem) * max_tau_items)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dTwSt, (size_t)kzk::stage_twiddle_entries() * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dY, sizeof(YItem) * max_y_items)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dStatus, 256)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dSched, sizeof(double) * (nsched + 1))) != KZK_OK) {
         kzk_destroy(p);
         return st;
     }
-    p->n_tau_items = max_tau_items;
+    p->max_tau_items = max_tau_items;
 
     // coefficient schedules
     {
@@ -395,6 +397,15 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
             e = hipMemcpy(p->dTw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+        std::vector<double> st64(2 * (size_t)kzk::stage_twiddle_entries());
+        kzk::stage_twiddles(st64.data());
+        if (p->dtype == KZK_F32) {
+            std::vector<float> f(st64.begin(), st64.end());
+            e = hipMemcpy(p->dTwSt, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(p->dTwSt, st64.data(), st64.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     }
     if (hipMemset(p->dStatus, 0, 256) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     if ((st = layout(p)) != KZK_OK || (st = build_tables(p, 0, false)) != KZK_OK) {
@@ -420,6 +431,7 @@ kzk_status kzk_set_graph(kzk_plan* p, int32_t enable) {
 }
 
 int32_t kzk_get_y_threads(const kzk_plan* p) { return p ? p->y_threads : 0; }
+
 
 kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
     if (!p) return KZK_ERR_ARG;

@@ -1,12 +1,8 @@
 // fft.hpp -- device-side FFT building blocks for gfx950.
 //
-// Complex arithmetic, radix-2/4/8/16 DFTs held in registers, and one
-// Stockham autosort stage over data staged in LDS.  A length-n transform
-// (n a power of two, 16 <= n <= 8192) is done by n/16 threads, each of which
-// holds exactly 16 elements per stage: one radix-16 butterfly, or several
-// butterflies of the smaller tail radix.  Twiddles come from a table
-// tw[k] = exp(-2 pi i k / Ntw) built in FP64 on the host and stored in the
-// working precision; a stage of span Ns*R reads it with stride Ntw/(Ns*R).
+// Complex arithmetic, radix-2/4/8/16 DFTs held in registers, and Stockham
+// autosort stages over data staged in LDS.  Twiddle tables are built in FP64
+// on the host and stored in the working precision.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -118,72 +114,118 @@ template <int S, typename T> __device__ __forceinline__ cpx<T> twiddle(const cpx
 __device__ __forceinline__ int padi(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded(int n) { return n + n / 16; }
 
-// ---------------------------------------------------------------- one Stockham stage
-// Length-n transform stored at buf[base + idx * stride].  Thread t (< n/16)
-// takes butterflies j = t + b * n/16... for b < 16/R; the stage reads the
-// inputs of all its butterflies, waits, then writes the outputs, so the
-// transform runs in place.  Every thread of the block must call it (barriers).
-template <typename T, int R, int S>
-__device__ __forceinline__ void stockham_stage(cpx<T>* buf, int base, int stride, int n, int Ns, int t,
-                                               bool active, const cpx<T>* __restrict__ tw, int log2_tw_span) {
-    constexpr int PER = 16 / R;
-    const int tpr = n >> 4;
-    const int nR = n / R;
+// ---------------------------------------------------------------- Stockham stages
+// A length-n transform (n = 2^LN, 16 <= n <= 8192) at logical LDS positions
+// base + idx (base a multiple of 16), done by n/16 threads t, each holding 16
+// elements per stage: radix-16 stages first, then one tail stage of radix
+// 2, 4 or 8.  Stage sizes are compile-time, so every LDS access of a thread
+// is one padded base address plus an immediate offset.  A stage reads the
+// inputs of all its butterflies, waits, then writes the outputs (in place).
+// Twiddles of the stage with span Ns*R come from a per-stage table
+// twst[off + k*R + s] = exp(-2 pi i k s / (Ns R)) (k < Ns, s < R).
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+// sum of Ns*R over the stages with Ns > 1 of a length-2^LN transform
+__host__ __device__ constexpr int ct_stage_span_sum(int LN) {
+    int tot = 0, lg = 0;
+    while (lg < LN) {
+        const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
+        if (lg > 0) tot += 1 << (lg + lr);
+        lg += lr;
+    }
+    return tot;
+}
+// offset of the stage starting at Ns = 2^LG in the table of all sizes 2^4..2^13
+__host__ __device__ constexpr int ct_stage_offset(int LN, int LG) {
+    int o = 0;
+    for (int l = 4; l < LN; ++l) o += ct_stage_span_sum(l);
+    int lg = 0;
+    while (lg < LG) {
+        const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
+        if (lg > 0) o += 1 << (lg + lr);
+        lg += lr;
+    }
+    return o;
+}
+constexpr int CT_MIN_LN = 4, CT_MAX_LN = 13;
+constexpr int CT_TABLE_SIZE = ct_stage_offset(CT_MAX_LN + 1, 0);
+
+template <typename T, int S, int LN, int LG, int LR>
+__device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
+    constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
     cpx<T> v[PER][R];
     if (active) {
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
-            int j = t + b * tpr;
-            #pragma unroll
-            for (int s = 0; s < R; ++s) v[b][s] = buf[padi(base + (j + s * nR) * stride)];
+            const int j = t + b * tpr;
+            if constexpr (nR % 16 == 0) {
+                const int p = padi(base + j);
+                #pragma unroll
+                for (int s = 0; s < R; ++s) v[b][s] = buf[p + 17 * s * (nR / 16)];
+            } else {
+                #pragma unroll
+                for (int s = 0; s < R; ++s) v[b][s] = buf[padi(base + j + s * nR)];
+            }
         }
     }
     __syncthreads();
     if (active) {
-        // span = Ns * R; twiddle exp(S 2 pi i k s / span) = w(k * s * Ntw / span)
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
-            int j = t + b * tpr;
-            int k = j & (Ns - 1);
-            if (Ns > 1) {
+            const int j = t + b * tpr;
+            const int k = j & (Ns - 1);
+            if constexpr (Ns > 1) {
+                const cpx<T>* w = twst + ct_stage_offset(LN, LG) + k * R;
                 #pragma unroll
-                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], twiddle<S>(tw, (k * s) << log2_tw_span));
+                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], twiddle<S>(w, s));
             }
             Dft<T, R, S>::run(v[b]);
-            int d = (j - k) * R + k;
-            #pragma unroll
-            for (int s = 0; s < R; ++s) buf[padi(base + (d + s * Ns) * stride)] = v[b][s];
+            if constexpr (Ns == 1) {
+                static_assert(R == 16, "first stage is radix 16");
+                const int p = padi(base + j * R);
+                #pragma unroll
+                for (int s = 0; s < R; ++s) buf[p + s] = v[b][s];
+            } else if constexpr (Ns % 16 == 0) {
+                const int p = padi(base + (j - k) * R + k);
+                #pragma unroll
+                for (int s = 0; s < R; ++s) buf[p + 17 * s * (Ns / 16)] = v[b][s];
+            } else {
+                #pragma unroll
+                for (int s = 0; s < R; ++s) buf[padi(base + (j - k) * R + k + s * Ns)] = v[b][s];
+            }
         }
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+template <typename T, int S, int LN, int LG>
+__device__ __forceinline__ void ct_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
+    if constexpr (LG < LN) {
+        constexpr int LR = (LN - LG) >= 4 ? 4 : (LN - LG);
+        ct_stage<T, S, LN, LG, LR>(buf, base, t, active, twst);
+        ct_stages<T, S, LN, LG + LR>(buf, base, t, active, twst);
+    }
+}
 
-// Full in-place length-n FFT (16 <= n <= 8192) of the sequence at logical
-// LDS positions base + idx * stride, done by threads t < n/16 where `active`.
-// log2_ntw = log2 of the twiddle table length (>= log2 n).
+// In-place length-n FFT (16 <= n <= 8192, a power of two) of the sequence at
+// logical LDS positions base .. base+n-1 (base a multiple of 16), done by the
+// threads t < n/16 where `active`; every thread of the block must call it.
+// S = -1: forward, S = +1: inverse (unnormalised).
 template <typename T, int S>
-__device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int stride, int n, int t, bool active,
-                                        const cpx<T>* __restrict__ tw, int log2_ntw) {
-    int Ns = 1;
-    int lg = 0;   // log2(Ns)
-    const int ln = ilog2(n);
-    while (Ns < n) {
-        int rem = ln - lg;
-        if (rem >= 4) {
-            stockham_stage<T, 16, S>(buf, base, stride, n, Ns, t, active, tw, log2_ntw - (lg + 4));
-            Ns <<= 4; lg += 4;
-        } else if (rem == 3) {
-            stockham_stage<T, 8, S>(buf, base, stride, n, Ns, t, active, tw, log2_ntw - (lg + 3));
-            Ns <<= 3; lg += 3;
-        } else if (rem == 2) {
-            stockham_stage<T, 4, S>(buf, base, stride, n, Ns, t, active, tw, log2_ntw - (lg + 2));
-            Ns <<= 2; lg += 2;
-        } else {
-            stockham_stage<T, 2, S>(buf, base, stride, n, Ns, t, active, tw, log2_ntw - (lg + 1));
-            Ns <<= 1; lg += 1;
-        }
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int n, int t, bool active,
+                                        const cpx<T>* __restrict__ twst) {
+    switch (ilog2(n)) {
+    case 4: ct_stages<T, S, 4, 0>(buf, base, t, active, twst); break;
+    case 5: ct_stages<T, S, 5, 0>(buf, base, t, active, twst); break;
+    case 6: ct_stages<T, S, 6, 0>(buf, base, t, active, twst); break;
+    case 7: ct_stages<T, S, 7, 0>(buf, base, t, active, twst); break;
+    case 8: ct_stages<T, S, 8, 0>(buf, base, t, active, twst); break;
+    case 9: ct_stages<T, S, 9, 0>(buf, base, t, active, twst); break;
+    case 10: ct_stages<T, S, 10, 0>(buf, base, t, active, twst); break;
+    case 11: ct_stages<T, S, 11, 0>(buf, base, t, active, twst); break;
+    case 12: ct_stages<T, S, 12, 0>(buf, base, t, active, twst); break;
+    default: ct_stages<T, S, 13, 0>(buf, base, t, active, twst); break;
     }
 }
 

@@ -9,9 +9,9 @@ namespace kzk {
 // Status bits latched by the kernels (vector atomics on a device word).
 enum : unsigned { ST_CFL = 1u, ST_NONFINITE = 2u };
 
-// Threads of a tau-pass block.  A tau-line of n_tau reals is handled as a
-// complex sequence of M = n_tau/2 points by M/16 threads; a block holds
-// 256*16 = 4096 complex points, i.e. 8192/n_tau lines.
+// A tau-line of n_tau reals is handled as a complex sequence of M = n_tau/2
+// points by M/16 threads; a tau-pass block holds TAU_THREADS*16 complex
+// points, i.e. 8192/n_tau lines.
 constexpr int TAU_THREADS = 256;
 
 // One solve of a (possibly batched) plan, as the kernels see it.
@@ -19,7 +19,7 @@ struct InstDesc {
     int n_tau, n_y;        // grid points along tau and y
     int M, Nh;             // M = n_tau/2 complex tau-modes (packed), Nh = n_y/2 + 1
     int W, log2W;          // y-pass tile width (columns per block)
-    int rows_per_tau_block;
+    int rows_per_tau_block;  // lines per tau-pass block (TAU_THREADS * 16 / M)
     int pad0;
     long long off_state;   // complex offset of this solve in the C, B, P arrays
     long long off_u;       // real offset of this solve in the packed physical field
@@ -36,30 +36,34 @@ struct TauItem { int inst, row0; };
 struct YItem { int inst, m0; };
 
 // Launchers (kernels.hip).  All enqueue on `s` and return hipSuccess or the
-// launch error.
+// launch error.  tw: twiddles exp(-2 pi i k / 2^log2_ntw); twst: per-stage
+// Stockham twiddles of all transform lengths 2^4 .. 2^13 (fft.hpp).
 template <typename T>
-hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items,
-                      const T* u_in, T* u_out, const void* Cin, void* Bout, const void* tw,
-                      int log2_ntw, int node, int tiled, unsigned* status, hipStream_t s);
+hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+                      T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
+                      int node, int tiled, unsigned* status, hipStream_t s);
 
 template <typename T>
-hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    void* C, const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw,
-                    hipStream_t s);
+hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
+                    const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s);
 
 template <typename T>
-hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step,
-                         hipStream_t s);
+hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step, hipStream_t s);
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
-                          const void* Rin, const T* ustore, void* out, const void* tw, int log2_ntw, int node,
-                          unsigned* status, hipStream_t s);
+                          const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
+                          int log2_ntw, int node, unsigned* status, hipStream_t s);
 
 template <typename T>
 hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
-                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
-                        hipStream_t s);
+                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s);
+
+// Number of complex entries of the per-stage twiddle table (all lengths).
+int stage_twiddle_entries();
+// Fill it (FP64) in the layout of fft.hpp: for each length 2^LN (LN = 4..13),
+// for each stage with Ns > 1, entries exp(-2 pi i k s / (Ns R)) at k*R + s.
+void stage_twiddles(double* out_interleaved);
 
 // Block sizes of the y-pass for which kernels are compiled.
 bool y_threads_supported(int dtype_is_f64, int nt);

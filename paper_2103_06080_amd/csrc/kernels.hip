@@ -197,7 +197,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
                                                           const TauItem* __restrict__ items,
                                                           const T* __restrict__ u_in, T* __restrict__ u_out,
                                                           const cpx<T>* __restrict__ Cin, cpx<T>* __restrict__ Bout,
-                                                          const cpx<T>* __restrict__ tw, int log2_ntw, int node,
+                                                          const cpx<T>* __restrict__ tw,
+                                                          const cpx<T>* __restrict__ twst, int log2_ntw, int node,
                                                           int tiled, unsigned* __restrict__ status) {
     __shared__ alignas(32) cpx<T> lds[padded(TAU_THREADS * 16)];
     __shared__ T redT[4];
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         bad = line_or(bad, tpr, redI);
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
-        lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
+        lds_fft<T, -1>(lds, base, M, t, active, twst);
         if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
         return;
     }
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     // inverse tau-transform of C~ into the line buffer
     if (active) c2r_pre(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
     __syncthreads();
-    lds_fft<T, 1>(lds, base, 1, M, t, active, tw, log2_ntw);
+    lds_fft<T, 1>(lds, base, M, t, active, twst);
 
     if (MODE == 1 || MODE == 3) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         if (active && c < Nc) lds_quad_st(lds, base, c, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
     }
     __syncthreads();
-    lds_fft<T, -1>(lds, base, 1, M, t, active, tw, log2_ntw);
+    lds_fft<T, -1>(lds, base, M, t, active, twst);
     if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
 }
 
@@ -328,8 +329,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 // A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows.
 // The mixed spectra C~, B~ (tau-spectral, y-physical) are stored in column
 // tiles [m / W][y][m % W], so the tile is one contiguous block of W * n_y
-// values, staged in LDS in the same order (lds[y * W + c]); W * n_y / 16
-// threads run the y-FFTs.  The fully spectral state U and the stage value P
+// values; in LDS each column is contiguous (logical c * n_y + y) and n_y/16
+// threads run its y-FFT.  The fully spectral state U and the stage value P
 // are stored tile-contiguously at [m0 * n_y + e] in the same element order
 // (e = y-wavenumber index * W + c).  The multiplier tables are stored per
 // tile as tab[m0 * Nh + n * W + c] (n = |ky index|, the symbol is even in
@@ -348,16 +349,16 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
                                                cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
                                                cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
                                                const cpx<T>* __restrict__ tabs,
-                                               const cpx<T>* __restrict__ tw, int log2_ntw) {
+                                               const cpx<T>* __restrict__ twst) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
     const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
     const int m0 = it.m0;
     const int tid = threadIdx.x;
-    const int nthr = W * (Ny >> 4);
-    const bool act = tid < nthr;
-    const int c = tid & (W - 1), t = tid >> lw;
+    const int lt = ilog2(Ny) - 4;                 // log2 of the FFT threads per column
+    const bool act = tid < (W << lt);
+    const int fc = tid >> lt, ft = tid & ((1 << lt) - 1);
     const int ne = W * Ny;
     const long long to = d.off_state + (long long)m0 * Ny;
     const cpx<T>* Bt = B + to;
@@ -368,44 +369,62 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     const cpx<T>* tP1 = tE + d.tab_stride;
     const cpx<T>* tP2 = tE + 2 * d.tab_stride;
     const bool col0 = (m0 == 0);
-    const int half = Ny >> 1;
+    // tile element e = j * W + c (global order) <-> LDS column c at logical c * Ny + j
+#define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
     if (STAGE == 0) {
-        for (int e = tid; e < ne; e += NT) lds[padi(e)] = Ct[e];
+        for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = Ct[e];
         __syncthreads();
-        lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+        lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
         for (int e = tid; e < ne; e += NT)
-            Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[padi(e)];
+            Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
         return;
     }
 
-    for (int e = tid; e < ne; e += NT) lds[padi(e)] = Bt[e];
+    for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = Bt[e];
     __syncthreads();
-    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
-    #pragma unroll 4
-    for (int e = tid; e < ne; e += NT) {
-        const int j = e >> lw, cc = e & (W - 1);
-        const int n = j <= half ? j : Ny - j;
-        const int ti = n * W + cc;
-        const cpx<T> bh = lds[padi(e)];
+    lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
+    // combine: the symbol is even in ky, so one table row n serves y-wavenumber
+    // indices n and Ny - n
+    const int nh = Nh * W;
+    for (int h = tid; h < nh; h += NT) {
+        const int n = h >> lw, cc = h & (W - 1);
+        const bool keep_col = !(col0 && cc == 0);
+        const int j2 = (n == 0 || 2 * n == Ny) ? -1 : Ny - n;
         if (STAGE == 1) {
-            const cpx<T> EU = cmul(tE[ti], Ut[e]);
-            const cpx<T> p1 = tP1[ti], p2 = tP2[ti];
-            if (!(col0 && cc == 0)) Pt[e] = EU + cmul(p1 - p2, bh);
-            lds[padi(e)] = EU + cmul(p1, bh);
+            const cpx<T> E = tE[h], p1 = tP1[h], p2 = tP2[h];
+            const cpx<T> p12 = p1 - p2;
+            #pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int j = pass ? j2 : n;
+                if (j < 0) break;
+                const int e = j * W + cc, li = padi(cc * Ny + j);
+                const cpx<T> bh = lds[li];
+                const cpx<T> EU = cmul(E, Ut[e]);
+                if (keep_col) Pt[e] = EU + cmul(p12, bh);
+                lds[li] = EU + cmul(p1, bh);
+            }
         } else {
-            // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
-            // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
-            const cpx<T> un = Pt[e] + cmul(tP2[ti], bh);
-            if (!(col0 && cc == 0)) Ut[e] = (T)Ny * un;
-            lds[padi(e)] = un;
+            const cpx<T> p2 = tP2[h];
+            #pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int j = pass ? j2 : n;
+                if (j < 0) break;
+                const int e = j * W + cc, li = padi(cc * Ny + j);
+                // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
+                // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
+                const cpx<T> un = Pt[e] + cmul(p2, lds[li]);
+                if (keep_col) Ut[e] = (T)Ny * un;
+                lds[li] = un;
+            }
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
     for (int e = tid; e < ne; e += NT) {
-        if (!(col0 && (e & (W - 1)) == 0)) Ct[e] = lds[padi(e)];
+        if (!(col0 && (e & (W - 1)) == 0)) Ct[e] = lds[KZK_LI(e)];
     }
+#undef KZK_LI
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
         const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
@@ -605,7 +624,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
                                                               const cpx<T>* __restrict__ Rin,
                                                               const T* __restrict__ ustore,
                                                               cpx<T>* __restrict__ out,
-                                                              const cpx<T>* __restrict__ tw, int log2_ntw, int node,
+                                                              const cpx<T>* __restrict__ tw,
+                                                              const cpx<T>* __restrict__ twst, int log2_ntw, int node,
                                                               unsigned* __restrict__ status) {
     __shared__ alignas(32) cpx<T> lds[2 * padded(TAU_THREADS * 16)];
     __shared__ T redT[4];
@@ -616,7 +636,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     const int tpr = M >> 4;
     const int r = threadIdx.x / tpr, t = threadIdx.x & (tpr - 1);
     const int row = it.row0 + r;
-    const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
+    const bool active = (r < (TAU_THREADS * 16) / M) && (row < d.n_y);
     const int gb = r * M;                          // cotangent line
     const int ub = TAU_THREADS * 16 + r * M;        // u line (second half of the buffer)
     const int Nc = M >> 1;
@@ -640,7 +660,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+    lds_fft<T, 1>(lds, gb, M, t, active, twst);
     mx = line_max(mx, tpr, redT);
     bad = line_or(bad, tpr, redI);
     if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
         // lam_n = r + J0^T t2, with r the inverse tau-transform of R~
         if (active) c2r_pre(Rin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
         __syncthreads();
-        lds_fft<T, 1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+        lds_fft<T, 1>(lds, gb, M, t, active, twst);
         #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int c = t + q * tpr;
@@ -669,7 +689,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
         if (active) lds_quad_st(lds, gb, c, quad<T>{{res[q][0], res[q][1], res[q][2], res[q][3]}});
     }
     __syncthreads();
-    lds_fft<T, -1>(lds, gb, 1, M, t, active, tw, log2_ntw);
+    lds_fft<T, -1>(lds, gb, M, t, active, twst);
     if (active) r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw);
 }
 
@@ -683,16 +703,16 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
                                                    const YItem* __restrict__ items, const cpx<T>* __restrict__ In,
                                                    cpx<T>* __restrict__ Lh, cpx<T>* __restrict__ Tout,
                                                    cpx<T>* __restrict__ Rout, const cpx<T>* __restrict__ tabs,
-                                                   const cpx<T>* __restrict__ tw, int log2_ntw) {
+                                                   const cpx<T>* __restrict__ twst) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
     const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
     const int m0 = it.m0;
     const int tid = threadIdx.x;
-    const int nthr = W * (Ny >> 4);
-    const bool act = tid < nthr;
-    const int c = tid & (W - 1), t = tid >> lw;
+    const int lt = ilog2(Ny) - 4;
+    const bool act = tid < (W << lt);
+    const int fc = tid >> lt, ft = tid & ((1 << lt) - 1);
     const int ne = W * Ny;
     const long long to = d.off_state + (long long)m0 * Ny;
     const cpx<T>* It = In + to;
@@ -703,10 +723,11 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
     const cpx<T>* tP2 = tE + 2 * d.tab_stride;
     const bool col0 = (m0 == 0);
     const int half = Ny >> 1;
+#define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
-    for (int e = tid; e < ne; e += NT) lds[padi(e)] = It[e];
+    for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = It[e];
     __syncthreads();
-    lds_fft<T, -1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
     cpx<T> keep[16];
     #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -715,37 +736,39 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
             const int j = e >> lw, cc = e & (W - 1);
             const int n = j <= half ? j : Ny - j;
             const int ti = n * W + cc;
-            cpx<T> X = lds[padi(e)];
+            const int li = KZK_LI(e);
+            cpx<T> X = lds[li];
             if (STAGE == 1) {
                 if (!(col0 && cc == 0)) Lt[e] = X;
-                lds[padi(e)] = cmulc(X, tP2[ti]);
+                lds[li] = cmulc(X, tP2[ti]);
             } else {
                 cpx<T> L = Lt[e];
                 cpx<T> p1 = tP1[ti], p2 = tP2[ti];
-                lds[padi(e)] = cmulc(L, p1 - p2) + cmulc(X, p1);
+                lds[li] = cmulc(L, p1 - p2) + cmulc(X, p1);
                 keep[q] = cmulc(L + X, tE[ti]);
             }
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+    lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
     for (int e = tid; e < ne; e += NT) {
-        if (!(col0 && (e & (W - 1)) == 0)) Tt[e] = lds[padi(e)];
+        if (!(col0 && (e & (W - 1)) == 0)) Tt[e] = lds[KZK_LI(e)];
     }
     if (STAGE == 2) {
         __syncthreads();
         #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + q * NT;
-            if (e < ne) lds[padi(e)] = keep[q];
+            if (e < ne) lds[KZK_LI(e)] = keep[q];
         }
         __syncthreads();
-        lds_fft<T, 1>(lds, c, W, Ny, t, act, tw, log2_ntw);
+        lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
         cpx<T>* Rt = Rout + to;
         for (int e = tid; e < ne; e += NT) {
-            if (!(col0 && (e & (W - 1)) == 0)) Rt[e] = lds[padi(e)];
+            if (!(col0 && (e & (W - 1)) == 0)) Rt[e] = lds[KZK_LI(e)];
         }
     }
+#undef KZK_LI
     if (col0) {
         const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
         for (int y = tid; y < Ny; y += NT) {
@@ -838,18 +861,19 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
 
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
-                      T* u_out, const void* Cin, void* Bout, const void* tw, int log2_ntw, int node, int tiled,
-                      unsigned* status, hipStream_t s) {
+                      T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
+                      int node, int tiled, unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     dim3 g(n_items), b(TAU_THREADS);
     const cpx<T>* ci = static_cast<const cpx<T>*>(Cin);
     cpx<T>* bo = static_cast<cpx<T>*>(Bout);
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
-    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
-    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
-    case 3: hipLaunchKernelGGL((tau_kernel<T, 3>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, log2_ntw, node, tiled, status); break;
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 3: hipLaunchKernelGGL((tau_kernel<T, 3>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -857,21 +881,20 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 
 template <typename T, int NT>
 static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                              const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw,
-                              hipStream_t s) {
+                              const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
     dim3 g(n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
     cpx<T>* p = static_cast<cpx<T>*>(P);
     cpx<T>* u = static_cast<cpx<T>*>(U);
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
-    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
     return hipGetLastError();
 }
 
@@ -882,14 +905,14 @@ bool y_threads_supported(int is_f64, int nt) {
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                    const void* B, void* P, void* U, const void* tabs, const void* tw, int log2_ntw, hipStream_t s) {
+                    const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (nt) {
-    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
-    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
+    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
+    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, tw, log2_ntw, s);
+            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -905,72 +928,88 @@ hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* ta
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
-                          const void* Rin, const T* ustore, void* out, const void* tw, int log2_ntw, int node,
-                          unsigned* status, hipStream_t s) {
+                          const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
+                          int log2_ntw, int node, unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     dim3 g(n_items), b(TAU_THREADS);
     const cpx<T>* ti = static_cast<const cpx<T>*>(Tin);
     const cpx<T>* ri = static_cast<const cpx<T>*>(Rin);
     cpx<T>* o = static_cast<cpx<T>*>(out);
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((tau_adj_kernel<T, 1>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, log2_ntw, node, status);
+        hipLaunchKernelGGL((tau_adj_kernel<T, 1>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
     else
-        hipLaunchKernelGGL((tau_adj_kernel<T, 2>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, log2_ntw, node, status);
+        hipLaunchKernelGGL((tau_adj_kernel<T, 2>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
     return hipGetLastError();
 }
 
 template <typename T, int NT>
 static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
-                                  void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
-                                  hipStream_t s) {
+                                  void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s) {
     dim3 g(n_items), b(NT);
     const cpx<T>* in = static_cast<const cpx<T>*>(In);
     cpx<T>* lh = static_cast<cpx<T>*>(Lh);
     cpx<T>* to = static_cast<cpx<T>*>(Tout);
     cpx<T>* ro = static_cast<cpx<T>*>(Rout);
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
-    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     else
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, w, log2_ntw);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
-                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* tw, int log2_ntw,
-                        hipStream_t s) {
+                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (nt) {
-    case 256: return launch_y_adj_nt<T, 256>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
-    case 512: return launch_y_adj_nt<T, 512>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
+    case 256: return launch_y_adj_nt<T, 256>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
+    case 512: return launch_y_adj_nt<T, 512>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_adj_nt<T, 1024>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, tw, log2_ntw, s);
+            return launch_y_adj_nt<T, 1024>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_tau_adj<float>(int, const InstDesc*, const TauItem*, int, const void*, const void*,
-                                          const float*, void*, const void*, int, int, unsigned*, hipStream_t);
-template hipError_t launch_tau_adj<double>(int, const InstDesc*, const TauItem*, int, const void*, const void*,
-                                           const double*, void*, const void*, int, int, unsigned*, hipStream_t);
-template hipError_t launch_y_adj<float>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,
-                                        void*, const void*, const void*, int, hipStream_t);
-template hipError_t launch_y_adj<double>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,
-                                         void*, const void*, const void*, int, hipStream_t);
-template hipError_t launch_tau<float>(int, const InstDesc*, const TauItem*, int, const float*, float*, const void*,
-                                      void*, const void*, int, int, int, unsigned*, hipStream_t);
-template hipError_t launch_tau<double>(int, const InstDesc*, const TauItem*, int, const double*, double*,
-                                       const void*, void*, const void*, int, int, int, unsigned*, hipStream_t);
-template hipError_t launch_y<float>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*,
-                                    const void*, const void*, int, hipStream_t);
-template hipError_t launch_y<double>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*,
-                                     const void*, const void*, int, hipStream_t);
-template hipError_t launch_tables<float>(const InstDesc*, int, int, void*, int, hipStream_t);
-template hipError_t launch_tables<double>(const InstDesc*, int, int, void*, int, hipStream_t);
+int stage_twiddle_entries() { return CT_TABLE_SIZE; }
+
+void stage_twiddles(double* out) {
+    for (int LN = CT_MIN_LN; LN <= CT_MAX_LN; ++LN) {
+        int lg = 0;
+        while (lg < LN) {
+            const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
+            if (lg > 0) {
+                const int off = ct_stage_offset(LN, lg), Ns = 1 << lg, R = 1 << lr;
+                for (int kk = 0; kk < Ns; ++kk)
+                    for (int s = 0; s < R; ++s) {
+                        const double a = -2.0 * KZK_PI * (double)(kk * s) / (double)(Ns * R);
+                        out[2 * (off + kk * R + s)] = cos(a);
+                        out[2 * (off + kk * R + s) + 1] = sin(a);
+                    }
+            }
+            lg += lr;
+        }
+    }
+}
+
+#define KZK_INSTANTIATE(T)                                                                                          \
+    template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
+                                      const void*, const void*, int, int, int, unsigned*, hipStream_t);              \
+    template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*, \
+                                    const void*, const void*, hipStream_t);                                          \
+    template hipError_t launch_tables<T>(const InstDesc*, int, int, void*, int, hipStream_t);                        \
+    template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
+                                          const T*, void*, const void*, const void*, int, int, unsigned*,            \
+                                          hipStream_t);                                                              \
+    template hipError_t launch_y_adj<T>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,    \
+                                        void*, const void*, const void*, hipStream_t);
+KZK_INSTANTIATE(float)
+KZK_INSTANTIATE(double)
+#undef KZK_INSTANTIATE
 
 }  // namespace kzk

@@ -172,6 +172,7 @@ class Plan:
     def y_threads(self) -> int:
         return lib().kzk_get_y_threads(self.h)
 
+
     # -- buffers
     @property
     def total(self) -> int:
