@@ -155,6 +155,17 @@ template <typename T, int S, int LN, int LG, int LR>
 __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
     constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
     cpx<T> v[PER][R];
+    cpx<T> wv[PER][R];   // twiddles, requested first: their latency overlaps the LDS reads and the barrier
+    if constexpr (Ns > 1) {
+        if (active) {
+            #pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const cpx<T>* w = twst + ct_stage_offset(LN, LG) + ((t + b * tpr) & (Ns - 1)) * R;
+                #pragma unroll
+                for (int s = 1; s < R; ++s) wv[b][s] = twiddle<S>(w, s);
+            }
+        }
+    }
     if (active) {
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
@@ -176,9 +187,8 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
             const int j = t + b * tpr;
             const int k = j & (Ns - 1);
             if constexpr (Ns > 1) {
-                const cpx<T>* w = twst + ct_stage_offset(LN, LG) + k * R;
                 #pragma unroll
-                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], twiddle<S>(w, s));
+                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], wv[b][s]);
             }
             Dft<T, R, S>::run(v[b]);
             if constexpr (Ns == 1) {

@@ -79,6 +79,62 @@ __device__ __forceinline__ T weno_face(T v0, T v1, T v2, T v3, T v4, T eps) {
     return (w0 * q0 + w1 * q1 + w2 * q2) * rcp((T)6 * (w0 + w1 + w2));
 }
 
+// WENO5-JS fluxes of one Lax-Friedrichs part at the eight faces 8g + k + 1/2
+// (k < 8) from the points u[0..15] = u_{8g-4} .. u_{8g+11}; SIGN = +1 adds
+// the reconstruction of f+ = (f + alpha u)/2 from the left, SIGN = -1 that of
+// f- = (f - alpha u)/2 from the right, into F[k] (SIGN = +1 initialises it).
+// The same values as weno_face, arranged so that work shared by adjacent
+// faces is done once per point: with first differences d_j = f_{j+1} - f_j
+// and second differences D_j = d_j - d_{j-1} of the split flux,
+//   beta_r = 13/12 D^2 + 1/4 b_r^2 with b_r = D +- 2 d or d_{j-1} + d_j,
+//   q_0 - q_1 = (D_{j-1} - D_j)/3,  q_2 - q_1 = (D_j - D_{j+1})/6,
+// and the face value is q_1 + w_0 (q_0 - q_1) + w_2 (q_2 - q_1).
+template <typename T, int SIGN>
+__device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alpha, T eps, T (&F)[8]) {
+    const T c1312 = (T)(13.0 / 12.0), sixth = (T)(1.0 / 6.0);
+    // split flux at the points 8g - 2 .. 8g + 10 (index j = point - 8g + 2)
+    T f[13];
+    #pragma unroll
+    for (int j = 0; j < 13; ++j) {
+        const T x = u[j + 2];
+        const T fp = x * fma(nlq, x, ha);           // (nl u^2/2 + alpha u)/2
+        f[j] = SIGN > 0 ? fp : fma(-alpha, x, fp);  // (nl u^2/2 - alpha u)/2
+    }
+    T dd[12], D2[12], A[12], G[12];
+    #pragma unroll
+    for (int j = 0; j < 12; ++j) dd[j] = f[j + 1] - f[j];
+    #pragma unroll
+    for (int j = 1; j < 12; ++j) {
+        D2[j] = dd[j] - dd[j - 1];
+        A[j] = fma(c1312 * D2[j], D2[j], eps);
+    }
+    #pragma unroll
+    for (int j = 1; j < 11; ++j) G[j] = D2[j] - D2[j + 1];
+    #pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        // upwind point c, stencil neighbours a (upwind side) and b (downwind side)
+        const int c = SIGN > 0 ? k + 2 : k + 3;
+        const int a = c - SIGN, b = c + SIGN;
+        // d between c and a / c and b, oriented along the stencil
+        const T dca = SIGN > 0 ? dd[a] : -dd[c];     // f_c - f_a
+        const T dbc = SIGN > 0 ? dd[c] : -dd[b];     // f_b - f_c
+        const T b0 = fma((T)0.5, D2[a], dca);
+        const T b1 = (T)0.5 * (dca + dbc);
+        const T b2 = fma((T)0.5, D2[b], -dbc);
+        T s0 = fma(b0, b0, A[a]), s1 = fma(b1, b1, A[c]), s2 = fma(b2, b2, A[b]);
+        s0 *= s0; s1 *= s1; s2 *= s2;
+        const T t12 = s1 * s2, t02 = s0 * s2, t01 = s0 * s1;
+        // 30 (0.1 t12 + 0.6 t02 + 0.3 t01)
+        const T den = fma((T)3, t12, fma((T)18, t02, (T)9 * t01));
+        // 30 [0.1 t12 (q0 - q1) + 0.3 t01 (q2 - q1)]
+        const T Ga = SIGN > 0 ? G[a] : -G[c], Gc = SIGN > 0 ? G[c] : -G[b];
+        const T num = fma(t12, Ga, t01 * ((T)1.5 * Gc));
+        const T q1 = fma(sixth, fma((T)2, dbc, dca), f[c]);
+        const T r = fma(num, rcp(den), q1);
+        F[k] = SIGN > 0 ? r : F[k] + r;
+    }
+}
+
 // ------------------------------------------------------------------ block helpers
 
 // Max over the tpr threads of one line (lines are aligned groups of tpr
@@ -149,38 +205,48 @@ struct SpecIdx {
 template <typename T>
 __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int M, int t,
                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
-    const int lg_n = ilog2(2 * M);
-    for (int k = t; k <= (M >> 1); k += tpr) {
+    // pairs k = t + q*tpr <= M/2, q < 9 (tpr = M/16); all loads of the thread are
+    // issued before any is used, so their latencies overlap
+    const int sh = log2_ntw - ilog2(2 * M);
+    constexpr int Q = 9;
+    cpx<T> xk[Q], xm[Q], wv[Q];
+    #pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = min(t + q * tpr, M >> 1);
+        xk[q] = X[ix(k)];
+        xm[q] = X[ix((M - k) & (M - 1))];
+        wv[q] = tw[k << sh];
+    }
+    #pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = t + q * tpr;
+        if (k > (M >> 1)) continue;
         if (k == 0) {
-            cpx<T> s = X[0];
+            const cpx<T> s = xk[q];
             lds[padi(base)] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
             continue;
         }
-        cpx<T> xk = X[ix(k)], xm = X[ix(M - k)];
-        cpx<T> A = {xk.x + xm.x, xk.y - xm.y};
-        cpx<T> D = {xk.x - xm.x, xk.y + xm.y};
-        cpx<T> w = conj(tw[k << (log2_ntw - lg_n)]);      // e^{+2 pi i k/N}
-        cpx<T> P = mul_si<1>(cmul(w, D));
-        cpx<T> zk = A + P;
-        lds[padi(base + k)] = inv_n * zk;
-        if (2 * k != M) {
-            cpx<T> zm = conj(A - P);
-            lds[padi(base + M - k)] = inv_n * zm;
-        }
+        const cpx<T> A = {xk[q].x + xm[q].x, xk[q].y - xm[q].y};
+        const cpx<T> D = {xk[q].x - xm[q].x, xk[q].y + xm[q].y};
+        const cpx<T> P = mul_si<1>(cmul(conj(wv[q]), D));    // i e^{+2 pi i k/N} D
+        lds[padi(base + k)] = inv_n * (A + P);
+        if (2 * k != M) lds[padi(base + M - k)] = inv_n * conj(A - P);
     }
 }
 
 template <typename T>
 __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int M, int t,
                                          int tpr, const cpx<T>* __restrict__ tw, int log2_ntw) {
-    const int lg_n = ilog2(2 * M);
-    for (int k = t; k <= (M >> 1); k += tpr) {
-        cpx<T> zk = lds[padi(base + k)];
-        cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
-        cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
-        cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
-        cpx<T> w = tw[k << (log2_ntw - lg_n)];             // e^{-2 pi i k/N}
-        cpx<T> Q = mul_si<1>(cmul(w, D));
+    const int sh = log2_ntw - ilog2(2 * M);
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int k = t + q * tpr;
+        if (k > (M >> 1)) continue;
+        const cpx<T> zk = lds[padi(base + k)];
+        const cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
+        const cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+        const cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
+        const cpx<T> Q = mul_si<1>(cmul(tw[k << sh], D));    // i e^{-2 pi i k/N} D
         if (k == 0) {
             X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
             continue;
@@ -219,12 +285,17 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     if (MODE == 0) {
         const quad<T>* ug = reinterpret_cast<const quad<T>*>(u_in + d.off_u + (long long)row * N);
         int bad = 0;
-        if (active)
-            for (int c = t; c < Nc; c += tpr) {
-                quad<T> v = ug[c];
-                bad |= !(finite_val(v.v[0]) && finite_val(v.v[1]) && finite_val(v.v[2]) && finite_val(v.v[3]));
-                lds_quad_st(lds, base, c, v);
+        if (active) {
+            quad<T> v[8];
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = ug[t + q * tpr];
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                bad |= !(finite_val(v[q].v[0]) && finite_val(v[q].v[1]) && finite_val(v[q].v[2]) &&
+                         finite_val(v[q].v[3]));
+                lds_quad_st(lds, base, t + q * tpr, v[q]);
             }
+        }
         bad = line_or(bad, tpr, redI);
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
@@ -240,23 +311,27 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 
     if (MODE == 1 || MODE == 3) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
-        if (active)
-            for (int c = t; c < Nc; c += tpr) ug[c] = lds_quad(lds, base, c);
+        if (active) {
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) ug[t + q * tpr] = lds_quad(lds, base, t + q * tpr);
+        }
         if (MODE == 1) return;
     }
 
     // ---- LF speed alpha = |nl(x_node)| max|u| over the line (exact in any precision)
     T mx = 0;
     int bad = 0;
-    if (active)
-        for (int c = t; c < Nc; c += tpr) {
-            quad<T> v = lds_quad(lds, base, c);
+    if (active) {
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const quad<T> v = lds_quad(lds, base, t + q * tpr);
             #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 bad |= !finite_val(v.v[i]);
                 mx = tmax(mx, (T)fabs(v.v[i]));
             }
         }
+    }
     mx = line_max(mx, tpr, redT);
     bad = line_or(bad, tpr, redI);
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
@@ -269,56 +344,59 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         if (f) atomicOr(status, f);
     }
 
-    // ---- WENO5 fluxes at the faces 4c + k + 1/2 of my chunks
+    // ---- WENO5 fluxes at the faces 8g + k + 1/2 (k < 8) of my groups g = t + q*tpr (q < 4)
     const T eps = (T)d.weno_eps;
-    T F[8][4];
+    const T nlq = (T)0.25 * nlT, ha = (T)0.5 * alpha;
+    T F[4][8];
     #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = t + q * tpr;
-        if (active && c < Nc) {
-            quad<T> a = lds_quad(lds, base, (c - 1) & (Nc - 1)), b = lds_quad(lds, base, c),
-                    e = lds_quad(lds, base, (c + 1) & (Nc - 1));
-            T u[12] = {a.v[0], a.v[1], a.v[2], a.v[3], b.v[0], b.v[1], b.v[2], b.v[3],
-                       e.v[0], e.v[1], e.v[2], e.v[3]};
-            T fp[12], fm[12];
+    for (int q = 0; q < 4; ++q) {
+        const int g = t + q * tpr;
+        if (active) {
+            // points 8g - 4 .. 8g + 11
+            T u[16];
             #pragma unroll
-            for (int i = 2; i <= 10; ++i) {
-                T f = (T)0.5 * nlT * u[i] * u[i];
-                fp[i] = (T)0.5 * (f + alpha * u[i]);
-                fm[i] = (T)0.5 * (f - alpha * u[i]);
+            for (int h = 0; h < 4; ++h) {
+                const quad<T> v = lds_quad(lds, base, (2 * g - 1 + h) & (Nc - 1));
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) u[4 * h + i] = v.v[i];
             }
-            #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                F[q][k] = weno_face(fp[k + 2], fp[k + 3], fp[k + 4], fp[k + 5], fp[k + 6], eps) +
-                          weno_face(fm[k + 7], fm[k + 6], fm[k + 5], fm[k + 4], fm[k + 3], eps);
+            weno_group<T, 1>(u, nlq, ha, alpha, eps, F[q]);
+            weno_group<T, -1>(u, nlq, ha, alpha, eps, F[q]);
         }
     }
     __syncthreads();
     #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = t + q * tpr;
-        if (active && c < Nc) lds_quad_st(lds, base, c, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
+    for (int q = 0; q < 4; ++q) {
+        const int g = t + q * tpr;
+        if (active) {
+            lds_quad_st(lds, base, 2 * g, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
+            lds_quad_st(lds, base, 2 * g + 1, quad<T>{{F[q][4], F[q][5], F[q][6], F[q][7]}});
+        }
     }
     __syncthreads();
     // b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau
     const T mdt = -(T)(1.0 / d.dtau);
     #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = t + q * tpr;
-        if (active && c < Nc) {
-            quad<T> f = lds_quad(lds, base, c);
-            T fprev = lds_quad(lds, base, (c - 1) & (Nc - 1)).v[3];
-            F[q][0] = mdt * (f.v[0] - fprev);
-            F[q][1] = mdt * (f.v[1] - f.v[0]);
-            F[q][2] = mdt * (f.v[2] - f.v[1]);
-            F[q][3] = mdt * (f.v[3] - f.v[2]);
+    for (int q = 0; q < 4; ++q) {
+        const int g = t + q * tpr;
+        if (active) {
+            T prev = lds_quad(lds, base, (2 * g - 1) & (Nc - 1)).v[3];
+            #pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const T f = F[q][i];
+                F[q][i] = mdt * (f - prev);
+                prev = f;
+            }
         }
     }
     __syncthreads();
     #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = t + q * tpr;
-        if (active && c < Nc) lds_quad_st(lds, base, c, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
+    for (int q = 0; q < 4; ++q) {
+        const int g = t + q * tpr;
+        if (active) {
+            lds_quad_st(lds, base, 2 * g, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
+            lds_quad_st(lds, base, 2 * g + 1, quad<T>{{F[q][4], F[q][5], F[q][6], F[q][7]}});
+        }
     }
     __syncthreads();
     lds_fft<T, -1>(lds, base, M, t, active, twst);
@@ -326,6 +404,36 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 }
 
 // ------------------------------------------------------------------ y-pass
+// Tile <-> LDS copies.  Element e = j * W + c of a tile (global order) sits
+// in LDS column c at logical c * n_y + j.  A thread moves the elements
+// e = tid + q * NT (q < 16; a tile holds at most 16 NT elements) and issues
+// all of its global loads before the first one is used.
+__device__ __forceinline__ int tile_li(int e, int W, int lw, int Ny) { return padi((e & (W - 1)) * Ny + (e >> lw)); }
+
+template <typename T, int NT>
+__device__ __forceinline__ void tile_load(cpx<T>* lds, const cpx<T>* __restrict__ g, int ne, int tid, int W, int lw,
+                                          int Ny, cpx<T> (&v)[16]) {
+    // out-of-range slots reload the last element (no branch around the loads)
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = g[min(tid + q * NT, ne - 1)];
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * NT;
+        if (e < ne) lds[tile_li(e, W, lw, Ny)] = v[q];
+    }
+}
+
+// skips column 0 of the first tile (col0), whose modes are handled pointwise
+template <typename T, int NT>
+__device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>* lds, int ne, int tid, int W, int lw,
+                                           int Ny, bool col0) {
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * NT;
+        if (e < ne && !(col0 && (e & (W - 1)) == 0)) g[e] = lds[tile_li(e, W, lw, Ny)];
+    }
+}
+
 // A block owns W adjacent tau-mode columns m0..m0+W-1 over all n_y rows.
 // The mixed spectra C~, B~ (tau-spectral, y-physical) are stored in column
 // tiles [m / W][y][m % W], so the tile is one contiguous block of W * n_y
@@ -372,58 +480,77 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     // tile element e = j * W + c (global order) <-> LDS column c at logical c * Ny + j
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
+    cpx<T> v[16];
     if (STAGE == 0) {
-        for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = Ct[e];
+        tile_load<T, NT>(lds, Ct, ne, tid, W, lw, Ny, v);
         __syncthreads();
         lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
-        for (int e = tid; e < ne; e += NT)
-            Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + q * NT;
+            if (e < ne) Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
+        }
         return;
     }
 
-    for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = Bt[e];
+    tile_load<T, NT>(lds, Bt, ne, tid, W, lw, Ny, v);
     __syncthreads();
     lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
-    // indices n and Ny - n
+    // indices n and Ny - n.  A thread has at most 9 half-tile items
+    // (Nh * W <= 8 NT + W); their global loads are issued before use.
     const int nh = Nh * W;
-    for (int h = tid; h < nh; h += NT) {
-        const int n = h >> lw, cc = h & (W - 1);
-        const bool keep_col = !(col0 && cc == 0);
-        const int j2 = (n == 0 || 2 * n == Ny) ? -1 : Ny - n;
-        if (STAGE == 1) {
-            const cpx<T> E = tE[h], p1 = tP1[h], p2 = tP2[h];
-            const cpx<T> p12 = p1 - p2;
+    constexpr int QH = 9;
+    #pragma unroll
+    for (int q0 = 0; q0 < QH; q0 += 3) {
+        cpx<T> tb[3][3], ua[3][2];
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int h = min(tid + (q0 + q) * NT, nh - 1);   // clamped: loads without a branch
+            const int n = h >> lw, cc = h & (W - 1);
+            const int j2 = (n == 0 || 2 * n == Ny) ? n : Ny - n;
+            if (STAGE == 1) {
+                tb[q][0] = tE[h];
+                tb[q][1] = tP1[h];
+                tb[q][2] = tP2[h];
+                ua[q][0] = Ut[n * W + cc];
+                ua[q][1] = Ut[j2 * W + cc];
+            } else {
+                tb[q][2] = tP2[h];
+                ua[q][0] = Pt[n * W + cc];
+                ua[q][1] = Pt[j2 * W + cc];
+            }
+        }
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int h = tid + (q0 + q) * NT;
+            if (!(q0 + q < QH && h < nh)) continue;
+            const int n = h >> lw, cc = h & (W - 1);
+            const bool keep_col = !(col0 && cc == 0);
+            const bool two = !(n == 0 || 2 * n == Ny);
             #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
-                const int j = pass ? j2 : n;
-                if (j < 0) break;
+                if (pass == 1 && !two) break;
+                const int j = pass ? Ny - n : n;
                 const int e = j * W + cc, li = padi(cc * Ny + j);
                 const cpx<T> bh = lds[li];
-                const cpx<T> EU = cmul(E, Ut[e]);
-                if (keep_col) Pt[e] = EU + cmul(p12, bh);
-                lds[li] = EU + cmul(p1, bh);
-            }
-        } else {
-            const cpx<T> p2 = tP2[h];
-            #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                const int j = pass ? j2 : n;
-                if (j < 0) break;
-                const int e = j * W + cc, li = padi(cc * Ny + j);
-                // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
-                // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
-                const cpx<T> un = Pt[e] + cmul(p2, lds[li]);
-                if (keep_col) Ut[e] = (T)Ny * un;
-                lds[li] = un;
+                if (STAGE == 1) {
+                    const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
+                    if (keep_col) Pt[e] = EU + cmul(tb[q][1] - tb[q][2], bh);
+                    lds[li] = EU + cmul(tb[q][1], bh);
+                } else {
+                    // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
+                    // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
+                    const cpx<T> un = ua[q][pass] + cmul(tb[q][2], bh);
+                    if (keep_col) Ut[e] = (T)Ny * un;
+                    lds[li] = un;
+                }
             }
         }
     }
     __syncthreads();
     lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
-    for (int e = tid; e < ne; e += NT) {
-        if (!(col0 && (e & (W - 1)) == 0)) Ct[e] = lds[KZK_LI(e)];
-    }
+    tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
 #undef KZK_LI
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
@@ -649,14 +776,17 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     int bad = 0;
     if (active) {
         const quad<T>* ug = reinterpret_cast<const quad<T>*>(ustore + d.off_u + (long long)row * N);
-        for (int c = t; c < Nc; c += tpr) {
-            quad<T> v = ug[c];
+        quad<T> v[8];
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = ug[t + q * tpr];
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) {
             #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                bad |= !finite_val(v.v[i]);
-                mx = tmax(mx, (T)fabs(v.v[i]));
+                bad |= !finite_val(v[q].v[i]);
+                mx = tmax(mx, (T)fabs(v[q].v[i]));
             }
-            lds_quad_st(lds, ub, c, v);
+            lds_quad_st(lds, ub, t + q * tpr, v[q]);
         }
     }
     __syncthreads();
@@ -725,10 +855,10 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
     const int half = Ny >> 1;
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
-    for (int e = tid; e < ne; e += NT) lds[KZK_LI(e)] = It[e];
+    cpx<T> keep[16];
+    tile_load<T, NT>(lds, It, ne, tid, W, lw, Ny, keep);
     __syncthreads();
     lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
-    cpx<T> keep[16];
     #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = tid + q * NT;
@@ -751,9 +881,7 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
     }
     __syncthreads();
     lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
-    for (int e = tid; e < ne; e += NT) {
-        if (!(col0 && (e & (W - 1)) == 0)) Tt[e] = lds[KZK_LI(e)];
-    }
+    tile_store<T, NT>(Tt, lds, ne, tid, W, lw, Ny, col0);
     if (STAGE == 2) {
         __syncthreads();
         #pragma unroll
@@ -763,10 +891,7 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
         }
         __syncthreads();
         lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
-        cpx<T>* Rt = Rout + to;
-        for (int e = tid; e < ne; e += NT) {
-            if (!(col0 && (e & (W - 1)) == 0)) Rt[e] = lds[KZK_LI(e)];
-        }
+        tile_store<T, NT>(Rout + to, lds, ne, tid, W, lw, Ny, col0);
     }
 #undef KZK_LI
     if (col0) {
