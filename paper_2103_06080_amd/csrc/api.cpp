@@ -39,6 +39,7 @@ struct kzk_plan {
     size_t state_elems = 0, tab_elems = 0;
     int ntw = 0, log2_ntw = 0;
     int y_threads = 0;
+    int y_grid = 0;                       // persistent y-pass blocks (resident at once)
     bool any_D_sched = false;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
@@ -148,6 +149,8 @@ kzk_status layout(kzk_plan* p) {
     if ((int)tau.size() > p->max_tau_items) return KZK_ERR_STATE;
     p->n_tau_items = (int)tau.size();
     p->n_y_items = (int)ys.size();
+    p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->device);
+    if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dTau, tau.data(), sizeof(TauItem) * tau.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dY, ys.data(), sizeof(YItem) * ys.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -184,10 +187,10 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
 hipError_t ypass(kzk_plan* p, int stage) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
-        return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP,
-                                    p->dU, p->dTab, p->dTwSt, p->stream);
-    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->dC, p->dB, p->dP, p->dU,
-                                 p->dTab, p->dTwSt, p->stream);
+        return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB,
+                                    p->dP, p->dU, p->dTab, p->dTwSt, p->stream);
+    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB, p->dP,
+                                 p->dU, p->dTab, p->dTwSt, p->stream);
 }
 
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).

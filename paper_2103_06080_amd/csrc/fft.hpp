@@ -122,7 +122,8 @@ __host__ __device__ constexpr int padded(int n) { return n + n / 16; }
 // is one padded base address plus an immediate offset.  A stage reads the
 // inputs of all its butterflies, waits, then writes the outputs (in place).
 // Twiddles of the stage with span Ns*R come from a per-stage table
-// twst[off + k*R + s] = exp(-2 pi i k s / (Ns R)) (k < Ns, s < R).
+// twst[off + s*Ns + k] = exp(-2 pi i k s / (Ns R)) (k < Ns, s < R), s-major so
+// that the lanes of a wave (consecutive k) read consecutive entries.
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
@@ -151,21 +152,40 @@ __host__ __device__ constexpr int ct_stage_offset(int LN, int LG) {
 constexpr int CT_MIN_LN = 4, CT_MAX_LN = 13;
 constexpr int CT_TABLE_SIZE = ct_stage_offset(CT_MAX_LN + 1, 0);
 
-template <typename T, int S, int LN, int LG, int LR>
-__device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
-    constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
-    cpx<T> v[PER][R];
-    cpx<T> wv[PER][R];   // twiddles, requested first: their latency overlaps the LDS reads and the barrier
-    if constexpr (Ns > 1) {
-        if (active) {
+// radix (log2) of the stage starting at Ns = 2^LG of a length-2^LN transform
+__host__ __device__ constexpr int ct_radix(int LN, int LG) { return (LN - LG) >= 4 ? 4 : (LN - LG); }
+
+// The twiddles a thread needs in the stage starting at Ns = 2^LG: PER blocks
+// of R - 1 values (at most 15), w[b * (R - 1) + s - 1] for s = 1 .. R-1.
+template <typename T, int S, int LN, int LG>
+__device__ __forceinline__ void ct_fetch(const cpx<T>* __restrict__ twst, int t, bool active, cpx<T> (&w)[15]) {
+    if constexpr (LG > 0 && LG < LN) {
+        constexpr int LR = ct_radix(LN, LG), R = 1 << LR, PER = 16 / R, tpr = (1 << LN) >> 4, Ns = 1 << LG;
+        // every thread loads (the index is in range for any t): a load under a
+        // branch would make the compiler wait for it at the branch's join
+        (void)active;
+        #pragma unroll
+        for (int b = 0; b < PER; ++b) {
+            const cpx<T>* p = twst + ct_stage_offset(LN, LG) + ((t + b * tpr) & (Ns - 1));
             #pragma unroll
-            for (int b = 0; b < PER; ++b) {
-                const cpx<T>* w = twst + ct_stage_offset(LN, LG) + ((t + b * tpr) & (Ns - 1)) * R;
-                #pragma unroll
-                for (int s = 1; s < R; ++s) wv[b][s] = twiddle<S>(w, s);
-            }
+            for (int s = 1; s < R; ++s) w[b * (R - 1) + s - 1] = twiddle<S>(p, s * Ns);
         }
     }
+}
+
+// One stage.  LA (look-ahead): its twiddles wc are already in registers and
+// those of the following stage are requested first (into wn), so that their
+// latency is covered by this stage's work; otherwise the stage requests its
+// own twiddles (into wc) before its LDS reads and barrier (fewer registers).
+template <typename T, int S, bool LA, int LN, int LG, int LR>
+__device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
+                                         cpx<T> (&wc)[15], cpx<T> (&wn)[15]) {
+    constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
+    if constexpr (LA)
+        ct_fetch<T, S, LN, LG + LR>(twst, t, active, wn);
+    else
+        ct_fetch<T, S, LN, LG>(twst, t, active, wc);
+    cpx<T> v[PER][R];
     if (active) {
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
@@ -188,7 +208,7 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
             const int k = j & (Ns - 1);
             if constexpr (Ns > 1) {
                 #pragma unroll
-                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], wv[b][s]);
+                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], wc[b * (R - 1) + s - 1]);
             }
             Dft<T, R, S>::run(v[b]);
             if constexpr (Ns == 1) {
@@ -209,33 +229,41 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
     __syncthreads();
 }
 
-template <typename T, int S, int LN, int LG>
-__device__ __forceinline__ void ct_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
+template <typename T, int S, bool LA, int LN, int LG>
+__device__ __forceinline__ void ct_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
+                                          cpx<T> (&wc)[15]) {
     if constexpr (LG < LN) {
-        constexpr int LR = (LN - LG) >= 4 ? 4 : (LN - LG);
-        ct_stage<T, S, LN, LG, LR>(buf, base, t, active, twst);
-        ct_stages<T, S, LN, LG + LR>(buf, base, t, active, twst);
+        constexpr int LR = ct_radix(LN, LG);
+        cpx<T> wn[15];
+        ct_stage<T, S, LA, LN, LG, LR>(buf, base, t, active, twst, wc, wn);
+        ct_stages<T, S, LA, LN, LG + LR>(buf, base, t, active, twst, wn);
     }
+}
+
+template <typename T, int S, bool LA, int LN>
+__device__ __forceinline__ void ct_fft(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
+    cpx<T> w0[15];   // the first stage (Ns = 1) has no twiddles
+    ct_stages<T, S, LA, LN, 0>(buf, base, t, active, twst, w0);
 }
 
 // In-place length-n FFT (16 <= n <= 8192, a power of two) of the sequence at
 // logical LDS positions base .. base+n-1 (base a multiple of 16), done by the
 // threads t < n/16 where `active`; every thread of the block must call it.
-// S = -1: forward, S = +1: inverse (unnormalised).
-template <typename T, int S>
+// S = -1: forward, S = +1: inverse (unnormalised).  LA: twiddle look-ahead.
+template <typename T, int S, bool LA = true>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int n, int t, bool active,
                                         const cpx<T>* __restrict__ twst) {
     switch (ilog2(n)) {
-    case 4: ct_stages<T, S, 4, 0>(buf, base, t, active, twst); break;
-    case 5: ct_stages<T, S, 5, 0>(buf, base, t, active, twst); break;
-    case 6: ct_stages<T, S, 6, 0>(buf, base, t, active, twst); break;
-    case 7: ct_stages<T, S, 7, 0>(buf, base, t, active, twst); break;
-    case 8: ct_stages<T, S, 8, 0>(buf, base, t, active, twst); break;
-    case 9: ct_stages<T, S, 9, 0>(buf, base, t, active, twst); break;
-    case 10: ct_stages<T, S, 10, 0>(buf, base, t, active, twst); break;
-    case 11: ct_stages<T, S, 11, 0>(buf, base, t, active, twst); break;
-    case 12: ct_stages<T, S, 12, 0>(buf, base, t, active, twst); break;
-    default: ct_stages<T, S, 13, 0>(buf, base, t, active, twst); break;
+    case 4: ct_fft<T, S, LA, 4>(buf, base, t, active, twst); break;
+    case 5: ct_fft<T, S, LA, 5>(buf, base, t, active, twst); break;
+    case 6: ct_fft<T, S, LA, 6>(buf, base, t, active, twst); break;
+    case 7: ct_fft<T, S, LA, 7>(buf, base, t, active, twst); break;
+    case 8: ct_fft<T, S, LA, 8>(buf, base, t, active, twst); break;
+    case 9: ct_fft<T, S, LA, 9>(buf, base, t, active, twst); break;
+    case 10: ct_fft<T, S, LA, 10>(buf, base, t, active, twst); break;
+    case 11: ct_fft<T, S, LA, 11>(buf, base, t, active, twst); break;
+    case 12: ct_fft<T, S, LA, 12>(buf, base, t, active, twst); break;
+    default: ct_fft<T, S, LA, 13>(buf, base, t, active, twst); break;
     }
 }
 

@@ -43,9 +43,13 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
                       int node, int tiled, unsigned* status, hipStream_t s);
 
+// y-pass over n_items column tiles with at most max_blocks persistent blocks
+// (0: one block per tile)
 template <typename T>
-hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                    const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s);
+hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
+                    void* C, const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s);
+// blocks of the y-pass kernels (block size nt) resident at once on the device
+int y_resident_blocks(int dtype_is_f64, int nt, int device);
 
 template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step, hipStream_t s);

@@ -404,6 +404,11 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 }
 
 // ------------------------------------------------------------------ y-pass
+// y-pass FFTs: twiddle look-ahead (more registers)
+constexpr bool Y_LOOKAHEAD = false;
+// persistent y-pass blocks load the next tile while working on the current one
+constexpr bool Y_PREFETCH = true;
+
 // Tile <-> LDS copies.  Element e = j * W + c of a tile (global order) sits
 // in LDS column c at logical c * n_y + j.  A thread moves the elements
 // e = tid + q * NT (q < 16; a tile holds at most 16 NT elements) and issues
@@ -420,6 +425,34 @@ __device__ __forceinline__ void tile_load(cpx<T>* lds, const cpx<T>* __restrict_
     for (int q = 0; q < 16; ++q) {
         const int e = tid + q * NT;
         if (e < ne) lds[tile_li(e, W, lw, Ny)] = v[q];
+    }
+}
+
+// The loads of a tile alone (into registers, consumed later by tile_put);
+// real and imaginary parts in separate arrays.
+// With live = false every load reads the tile's first element (the loads stay
+// unconditional, so no register copies wait for them).
+template <typename T, int NT>
+__device__ __forceinline__ void tile_fetch(const InstDesc* __restrict__ descs, const YItem it, bool live,
+                                           const cpx<T>* __restrict__ src, int tid, T (&vr)[16], T (&vi)[16]) {
+    const InstDesc& d = descs[it.inst];
+    const int ne = live ? d.W * d.n_y : 1;
+    const cpx<T>* g = src + d.off_state + (long long)it.m0 * d.n_y;
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const cpx<T> x = g[min(tid + q * NT, ne - 1)];
+        vr[q] = x.x;
+        vi[q] = x.y;
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void tile_put(cpx<T>* lds, const T (&vr)[16], const T (&vi)[16], int ne, int tid, int W,
+                                         int lw, int Ny) {
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * NT;
+        if (e < ne) lds[tile_li(e, W, lw, Ny)] = cpx<T>{vr[q], vi[q]};
     }
 }
 
@@ -454,16 +487,25 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // every array; its DC is invariant and its Nyquist multipliers are scalars.
 template <typename T, int NT, int STAGE>
 __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
-                                               cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
+                                               int n_items, cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
                                                cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
                                                const cpx<T>* __restrict__ tabs,
                                                const cpx<T>* __restrict__ twst) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
-    const YItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const int tid = threadIdx.x;
+    // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...; the
+    // input tile of the next one is loaded into registers while this one is
+    // transformed and combined, so its memory latency is hidden.
+    const cpx<T>* src = STAGE == 0 ? C : B;
+    T vr[16], vi[16];
+    int item = blockIdx.x;
+    if (Y_PREFETCH && item < n_items) tile_fetch<T, NT>(descs, items[item], true, src, tid, vr, vi);
+    for (; item < n_items; item += gridDim.x) {
+    if (!Y_PREFETCH) tile_fetch<T, NT>(descs, items[item], true, src, tid, vr, vi);
+    const YItem it = items[item];
     const InstDesc& d = descs[it.inst];
     const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
     const int m0 = it.m0;
-    const int tid = threadIdx.x;
     const int lt = ilog2(Ny) - 4;                 // log2 of the FFT threads per column
     const bool act = tid < (W << lt);
     const int fc = tid >> lt, ft = tid & ((1 << lt) - 1);
@@ -480,22 +522,24 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     // tile element e = j * W + c (global order) <-> LDS column c at logical c * Ny + j
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
-    cpx<T> v[16];
+    tile_put<T, NT>(lds, vr, vi, ne, tid, W, lw, Ny);
+    __syncthreads();
+    if (Y_PREFETCH) {
+        const bool more = item + (int)gridDim.x < n_items;
+        tile_fetch<T, NT>(descs, items[more ? item + gridDim.x : item], more, src, tid, vr, vi);
+    }
     if (STAGE == 0) {
-        tile_load<T, NT>(lds, Ct, ne, tid, W, lw, Ny, v);
-        __syncthreads();
-        lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
+        lds_fft<T, -1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
         #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + q * NT;
             if (e < ne) Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
         }
-        return;
+        __syncthreads();
+        continue;
     }
 
-    tile_load<T, NT>(lds, Bt, ne, tid, W, lw, Ny, v);
-    __syncthreads();
-    lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
+    lds_fft<T, -1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
     // indices n and Ny - n.  A thread has at most 9 half-tile items
     // (Nh * W <= 8 NT + W); their global loads are issued before use.
@@ -549,7 +593,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
+    lds_fft<T, 1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
     tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
 #undef KZK_LI
     if (col0) {
@@ -569,6 +613,8 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
                 Ut[o] = un;
             }
         }
+    }
+    __syncthreads();    // LDS reads of this tile are done before the next tile is written
     }
 }
 
@@ -1005,9 +1051,10 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 }
 
 template <typename T, int NT>
-static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                              const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
-    dim3 g(n_items), b(NT);
+static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
+                              void* C, const void* B, void* P, void* U, const void* tabs, const void* twst,
+                              hipStream_t s) {
+    dim3 g(max_blocks > 0 && max_blocks < n_items ? max_blocks : n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
     cpx<T>* p = static_cast<cpx<T>*>(P);
@@ -1015,12 +1062,36 @@ static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
     return hipGetLastError();
+}
+
+template <typename T, int NT>
+static int y_resident_nt(int device) {
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
+        return 0;
+    int lo = 1 << 30;
+    const void* fns[3] = {(const void*)y_kernel<T, NT, 0>, (const void*)y_kernel<T, NT, 1>,
+                          (const void*)y_kernel<T, NT, 2>};
+    for (const void* f : fns) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, NT, 0) != hipSuccess || per <= 0) return 0;
+        lo = per < lo ? per : lo;
+    }
+    return ncu * lo;
+}
+
+int y_resident_blocks(int is_f64, int nt, int device) {
+    switch (nt) {
+    case 256: return is_f64 ? y_resident_nt<double, 256>(device) : y_resident_nt<float, 256>(device);
+    case 512: return is_f64 ? y_resident_nt<double, 512>(device) : y_resident_nt<float, 512>(device);
+    case 1024: return is_f64 ? 0 : y_resident_nt<float, 1024>(device);
+    default: return 0;
+    }
 }
 
 bool y_threads_supported(int is_f64, int nt) {
@@ -1029,15 +1100,15 @@ bool y_threads_supported(int is_f64, int nt) {
 }
 
 template <typename T>
-hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, void* C,
-                    const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
+hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
+                    void* C, const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (nt) {
-    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
-    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
+    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
+    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, C, B, P, U, tabs, twst, s);
+            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -1113,8 +1184,8 @@ void stage_twiddles(double* out) {
                 for (int kk = 0; kk < Ns; ++kk)
                     for (int s = 0; s < R; ++s) {
                         const double a = -2.0 * KZK_PI * (double)(kk * s) / (double)(Ns * R);
-                        out[2 * (off + kk * R + s)] = cos(a);
-                        out[2 * (off + kk * R + s) + 1] = sin(a);
+                        out[2 * (off + s * Ns + kk)] = cos(a);
+                        out[2 * (off + s * Ns + kk) + 1] = sin(a);
                     }
             }
             lg += lr;
@@ -1125,8 +1196,8 @@ void stage_twiddles(double* out) {
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
                                       const void*, const void*, int, int, int, unsigned*, hipStream_t);              \
-    template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, void*, const void*, void*, void*, \
-                                    const void*, const void*, hipStream_t);                                          \
+    template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, int, void*, const void*, void*,   \
+                                    void*, const void*, const void*, hipStream_t);                                   \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, void*, int, hipStream_t);                        \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
