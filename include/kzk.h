@@ -116,7 +116,8 @@ kzk_status kzk_set_stream(kzk_plan *plan, void *hip_stream);
 kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
 
 /* Select the y-pass block size (256, 512 or 1024 threads; 1024 in FP32
- * only); rebuilds the tiled multiplier tables.  0 restores the default. */
+ * only); rebuilds the tiled multiplier tables.  0 restores the default: the
+ * smallest size whose column tiles are at least 32 bytes wide. */
 kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
 /* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is

@@ -131,7 +131,26 @@ kzk_status check_params(const kzk_params& q) {
     return KZK_OK;
 }
 
-int default_y_threads(int dtype) { return dtype == KZK_F32 ? 1024 : 512; }
+// Default y-pass block size: the smallest supported one whose column tiles
+// are at least 32 bytes wide (W complex values) in every instance, so that
+// the tau-pass reads and writes row segments of 32 bytes or more; smaller
+// blocks use less LDS, so more of them share a compute unit and their load,
+// transform and store phases overlap.
+int default_y_threads(const kzk_plan* p) {
+    const int cands[3] = {256, 512, 1024};
+    int last = 0;
+    for (int nt : cands) {
+        if (!kzk::y_threads_supported(p->dtype == KZK_F64, nt)) continue;
+        last = nt;
+        bool wide = true;
+        for (const InstDesc& d : p->desc) {
+            const int W = std::min(nt * 16 / d.n_y, d.M);
+            if (W < d.M && (size_t)W * 2 * p->esz < 32) wide = false;
+        }
+        if (wide) return nt;
+    }
+    return last;
+}
 
 // Descriptors, work lists and tables for the current y-pass block size.
 kzk_status layout(kzk_plan* p) {
@@ -295,7 +314,6 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
     p->nlsched.resize(n_inst);
     p->desc.resize(n_inst);
     p->u_off.resize(n_inst + 1);
-    p->y_threads = default_y_threads(p->dtype);
 
     size_t so = 0, uo = 0, to = 0, nsched = 0;
     int ntw = 0, max_tau_items = 0, max_y_items = 0;
@@ -411,6 +429,7 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
         if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     }
     if (hipMemset(p->dStatus, 0, 256) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+    p->y_threads = default_y_threads(p);
     if ((st = layout(p)) != KZK_OK || (st = build_tables(p, 0, false)) != KZK_OK) {
         kzk_destroy(p);
         return st;
@@ -438,7 +457,7 @@ int32_t kzk_get_y_threads(const kzk_plan* p) { return p ? p->y_threads : 0; }
 
 kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
     if (!p) return KZK_ERR_ARG;
-    if (threads == 0) threads = default_y_threads(p->dtype);
+    if (threads == 0) threads = default_y_threads(p);
     if (!kzk::y_threads_supported(p->dtype == KZK_F64, threads)) return KZK_ERR_ARG;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
     drop_graph(p);

@@ -194,13 +194,19 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 // Position of tau-mode k of one row in a spectral array: row-major rows of M
 // modes, or column tiles [k / W][y][k % W] (tile = W modes x n_y rows).
+// 32-bit arithmetic: within one instance every offset is below M n_y <= 2^24,
+// so the tile product fits a 24-bit multiply.
 struct SpecIdx {
-    int lw;
-    long long tile_stride;   // n_y * W for tiles, 0 for row-major
-    __device__ __forceinline__ long long operator()(int k) const {
-        return tile_stride ? (long long)(k >> lw) * tile_stride + (k & ((1 << lw) - 1)) : (long long)k;
+    int lw;              // log2 W (tiles); 30 for row-major (k >> 30 = 0)
+    unsigned mask;       // W - 1 (tiles); all ones below bit 30 for row-major
+    unsigned stride;     // n_y * W (tiles); 0 for row-major
+    __device__ __forceinline__ unsigned operator()(int k) const {
+        return __umul24((unsigned)k >> lw, stride) + ((unsigned)k & mask);
     }
 };
+__device__ __forceinline__ SpecIdx spec_idx(int log2W, int n_y, bool tiled) {
+    return tiled ? SpecIdx{log2W, (1u << log2W) - 1u, (unsigned)n_y << log2W} : SpecIdx{30, (1u << 30) - 1u, 0u};
+}
 
 template <typename T>
 __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int M, int t,
@@ -215,7 +221,7 @@ __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix
         const int k = min(t + q * tpr, M >> 1);
         xk[q] = X[ix(k)];
         xm[q] = X[ix((M - k) & (M - 1))];
-        wv[q] = tw[k << sh];
+        wv[q] = tw[(unsigned)k << sh];
     }
     #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -246,7 +252,7 @@ __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __
         const cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
         const cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
         const cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
-        const cpx<T> Q = mul_si<1>(cmul(tw[k << sh], D));    // i e^{-2 pi i k/N} D
+        const cpx<T> Q = mul_si<1>(cmul(tw[(unsigned)k << sh], D));    // i e^{-2 pi i k/N} D
         if (k == 0) {
             X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
             continue;
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
     const int base = r * M;
     const int Nc = M >> 1;   // chunks of 4 reals per line
-    const SpecIdx ix = {d.log2W, tiled ? (long long)d.n_y << d.log2W : 0};
+    const SpecIdx ix = spec_idx(d.log2W, d.n_y, tiled != 0);
     const long long so = d.off_state + (tiled ? ((long long)row << d.log2W) : (long long)row * M);
 
     if (MODE == 0) {
@@ -813,7 +819,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     const int gb = r * M;                          // cotangent line
     const int ub = TAU_THREADS * 16 + r * M;        // u line (second half of the buffer)
     const int Nc = M >> 1;
-    const SpecIdx ix = {d.log2W, (long long)d.n_y << d.log2W};
+    const SpecIdx ix = spec_idx(d.log2W, d.n_y, true);
     const long long so = d.off_state + ((long long)row << d.log2W);
 
     if (active) c2r_pre(Tin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
