@@ -184,8 +184,10 @@ kzk_status build_tables(kzk_plan* p, int step, bool only_scheduled) {
         int st = sched ? std::min<long long>(step, std::max<long long>(0, (long long)p->Dsched[i].size() - 1)) : 0;
         ProfScope ps(p, KZK_KIND_TABLES);
         hipError_t e = p->dtype == KZK_F32
-            ? kzk::launch_tables<float>(p->dDesc, i, (int)p->desc[i].tab_size, p->dTab, st, p->stream)
-            : kzk::launch_tables<double>(p->dDesc, i, (int)p->desc[i].tab_size, p->dTab, st, p->stream);
+            ? kzk::launch_tables<float>(p->dDesc, i, p->desc[i].W * p->desc[i].Nh, p->desc[i].M / p->desc[i].W,
+                                        p->dTab, st, p->stream)
+            : kzk::launch_tables<double>(p->dDesc, i, p->desc[i].W * p->desc[i].Nh, p->desc[i].M / p->desc[i].W,
+                                         p->dTab, st, p->stream);
         if (e != hipSuccess) return KZK_ERR_DEVICE;
     }
     return KZK_OK;

@@ -52,7 +52,8 @@ hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_it
 int y_resident_blocks(int dtype_is_f64, int nt, int device);
 
 template <typename T>
-hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step, hipStream_t s);
+hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
+                         hipStream_t s);
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,

@@ -138,7 +138,7 @@ __device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alph
 // ------------------------------------------------------------------ block helpers
 
 // Max over the tpr threads of one line (lines are aligned groups of tpr
-// consecutive threads; tpr is a power of two).  red: 4 LDS slots.
+// consecutive threads; tpr is a power of two).  red: one LDS slot per wave.
 template <typename T>
 __device__ __forceinline__ T line_max(T v, int tpr, T* red) {
     const int w = tpr < 64 ? tpr : 64;
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
                                                           const cpx<T>* __restrict__ twst, int log2_ntw, int node,
                                                           int tiled, unsigned* __restrict__ status) {
     __shared__ alignas(32) cpx<T> lds[padded(TAU_THREADS * 16)];
-    __shared__ T redT[4];
-    __shared__ int redI[4];
+    __shared__ T redT[TAU_THREADS / 64];
+    __shared__ int redI[TAU_THREADS / 64];
     // consecutive rows on one XCD: with column tiles, rows y..y+W-1 share cache lines
     const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
@@ -807,8 +807,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
                                                               const cpx<T>* __restrict__ twst, int log2_ntw, int node,
                                                               unsigned* __restrict__ status) {
     __shared__ alignas(32) cpx<T> lds[2 * padded(TAU_THREADS * 16)];
-    __shared__ T redT[4];
-    __shared__ int redI[4];
+    __shared__ T redT[TAU_THREADS / 64];
+    __shared__ int redI[TAU_THREADS / 64];
     const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
     const int M = d.M, N = 2 * M;
@@ -966,17 +966,22 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
 // ------------------------------------------------------------------ multiplier tables
 // phi-functions in FP64: Taylor series of phi2 (Horner) for |z| < 1, with
 // phi1 = 1 + z phi2 and e^z = 1 + z phi1; closed forms otherwise.
+// phi2 = sum_j z^j / (j+2)!; for |z| < 1 the terms beyond j = 17 add less
+// than 1/20! relative to phi2 ~ 1/2, far below the FP64 rounding unit.
+__host__ __device__ constexpr double inv_fact_plus2(int j) {
+    double f = 1.0;
+    for (int i = 2; i <= j + 2; ++i) f *= (double)i;
+    return 1.0 / f;
+}
 __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, cpx<double>& p2) {
     const cpx<double> z = {zr, zi};
     if (zr * zr + zi * zi < 1.0) {
-        // 1/(j+2)!, j = 0..20
-        double f = 1.0;
-        for (int j = 2; j <= 22; ++j) f *= (double)j;   // 22!
-        cpx<double> p = {1.0 / f, 0.0};
-        for (int j = 19; j >= 0; --j) {
-            f /= (double)(j + 3);                         // (j+2)!
+        constexpr int J = 17;
+        cpx<double> p = {inv_fact_plus2(J), 0.0};
+        #pragma unroll
+        for (int j = J - 1; j >= 0; --j) {
             p = cmul(z, p);
-            p.x += 1.0 / f;
+            p.x += inv_fact_plus2(j);
         }
         p2 = p;
         p1 = cmul(z, p2);
@@ -998,14 +1003,14 @@ __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, 
 template <typename T>
 __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict__ descs, int inst,
                                                      cpx<T>* __restrict__ tabs, int step) {
+    // blockIdx.y: column tile m0 = y W; x: position n * W + c within the tile
     const InstDesc& d = descs[inst];
-    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // storage order
-    if (o >= d.tab_size) return;
     const int W = d.W, Nh = d.Nh;
-    const long long tile = o / ((long long)W * Nh);
-    const int rem = (int)(o - tile * W * Nh);
-    const int n = rem / W, c = rem - n * W;
-    const int m = (int)tile * W + c;
+    const int rem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rem >= W * Nh) return;
+    const int n = rem >> d.log2W, c = rem & (W - 1);
+    const int m = (int)blockIdx.y * W + c;
+    const long long o = (long long)blockIdx.y * W * Nh + rem;   // storage order
     cpx<T>* tE = tabs + d.off_tab + o;
     cpx<T>* tP1 = tE + d.tab_stride;
     cpx<T>* tP2 = tE + 2 * d.tab_stride;
@@ -1121,9 +1126,10 @@ hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_it
 }
 
 template <typename T>
-hipError_t launch_tables(const InstDesc* d_desc, int inst, int n_elems, void* tabs, int step, hipStream_t s) {
-    if (n_elems <= 0) return hipSuccess;
-    dim3 g((n_elems + 255) / 256), b(256);
+hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
+                         hipStream_t s) {
+    if (per_tile <= 0 || n_tiles <= 0) return hipSuccess;
+    dim3 g((per_tile + 255) / 256, n_tiles), b(256);
     hipLaunchKernelGGL((tables_kernel<T>), g, b, 0, s, d_desc, inst, static_cast<cpx<T>*>(tabs), step);
     return hipGetLastError();
 }
@@ -1204,7 +1210,7 @@ void stage_twiddles(double* out) {
                                       const void*, const void*, int, int, int, unsigned*, hipStream_t);              \
     template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, int, void*, const void*, void*,   \
                                     void*, const void*, const void*, hipStream_t);                                   \
-    template hipError_t launch_tables<T>(const InstDesc*, int, int, void*, int, hipStream_t);                        \
+    template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
                                           hipStream_t);                                                              \
