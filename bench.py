@@ -53,16 +53,23 @@ def kernel_model(kind, n_tau, n_y, esz):
     return None, None
 
 
+def kernel_source_sha():
+    """sha256 over the device sources (kernels, FFT stages, shared descriptors)."""
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft.hpp", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2103_06080_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def pmc_traffic(kernel_kind, workload, dtype):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.json" % (kernel_kind, workload, dtype))
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2103_06080_amd", "csrc", "kernels.hip"), "rb").read()
-        if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        if rec.get("kernels_sha256") != kernel_source_sha():
             return None
         return rec.get("hbm_bytes_per_launch")
     except Exception:
