@@ -173,17 +173,21 @@ __device__ __forceinline__ void ct_fetch(const cpx<T>* __restrict__ twst, int t,
     }
 }
 
-// One stage.  LA (look-ahead): its twiddles wc are already in registers and
-// those of the following stage are requested first (into wn), so that their
-// latency is covered by this stage's work; otherwise the stage requests its
-// own twiddles (into wc) before its LDS reads and barrier (fewer registers).
-template <typename T, int S, bool LA, int LN, int LG, int LR>
+// Where a stage's twiddles come from.  TW_OWN: the stage requests them
+// (into wc) before its LDS reads and barrier.  TW_AHEAD: they are already in
+// wc and the stage requests those of the following stage first (into wn), so
+// that their latency is covered by this stage's work.  TW_HELD: wc holds the
+// forward (S = -1) twiddles for the whole transform, loaded once by the
+// caller; an inverse transform multiplies by their conjugates.
+enum { TW_OWN = 0, TW_AHEAD = 1, TW_HELD = 2 };
+
+template <typename T, int S, int TW, int LN, int LG, int LR>
 __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
                                          cpx<T> (&wc)[15], cpx<T> (&wn)[15]) {
     constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
-    if constexpr (LA)
+    if constexpr (TW == TW_AHEAD)
         ct_fetch<T, S, LN, LG + LR>(twst, t, active, wn);
-    else
+    else if constexpr (TW == TW_OWN)
         ct_fetch<T, S, LN, LG>(twst, t, active, wc);
     cpx<T> v[PER][R];
     if (active) {
@@ -208,7 +212,9 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
             const int k = j & (Ns - 1);
             if constexpr (Ns > 1) {
                 #pragma unroll
-                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], wc[b * (R - 1) + s - 1]);
+                for (int s = 1; s < R; ++s)
+                    v[b][s] = (TW == TW_HELD && S > 0) ? cmulc(v[b][s], wc[b * (R - 1) + s - 1])
+                                                       : cmul(v[b][s], wc[b * (R - 1) + s - 1]);
             }
             Dft<T, R, S>::run(v[b]);
             if constexpr (Ns == 1) {
@@ -229,21 +235,85 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
     __syncthreads();
 }
 
-template <typename T, int S, bool LA, int LN, int LG>
+template <typename T, int S, int TW, int LN, int LG>
 __device__ __forceinline__ void ct_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
                                           cpx<T> (&wc)[15]) {
     if constexpr (LG < LN) {
         constexpr int LR = ct_radix(LN, LG);
         cpx<T> wn[15];
-        ct_stage<T, S, LA, LN, LG, LR>(buf, base, t, active, twst, wc, wn);
-        ct_stages<T, S, LA, LN, LG + LR>(buf, base, t, active, twst, wn);
+        ct_stage<T, S, TW, LN, LG, LR>(buf, base, t, active, twst, wc, wn);
+        ct_stages<T, S, TW, LN, LG + LR>(buf, base, t, active, twst, wn);
     }
 }
 
-template <typename T, int S, bool LA, int LN>
+template <typename T, int S, int TW, int LN>
 __device__ __forceinline__ void ct_fft(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
     cpx<T> w0[15];   // the first stage (Ns = 1) has no twiddles
-    ct_stages<T, S, LA, LN, 0>(buf, base, t, active, twst, w0);
+    ct_stages<T, S, TW, LN, 0>(buf, base, t, active, twst, w0);
+}
+
+// Held twiddles: the stages with Ns > 1 of a length-2^LN transform
+// (LN <= 12: at most two of them, w[0] and w[1]).
+template <typename T, int LN, int LG, int I>
+__device__ __forceinline__ void ct_fetch_held(const cpx<T>* __restrict__ twst, int t, cpx<T> (&w)[2][15]) {
+    if constexpr (LG < LN) {
+        constexpr int LR = ct_radix(LN, LG);
+        if constexpr (LG > 0) {
+            static_assert(I < 2, "at most two stages with twiddles");
+            ct_fetch<T, -1, LN, LG>(twst, t, true, w[I]);
+            ct_fetch_held<T, LN, LG + LR, I + 1>(twst, t, w);
+        } else {
+            ct_fetch_held<T, LN, LG + LR, I>(twst, t, w);
+        }
+    }
+}
+
+template <typename T, int S, int LN, int LG, int I>
+__device__ __forceinline__ void ct_stages_held(cpx<T>* buf, int base, int t, bool active, cpx<T> (&w)[2][15]) {
+    if constexpr (LG < LN) {
+        constexpr int LR = ct_radix(LN, LG);
+        cpx<T> unused[15];
+        if constexpr (LG > 0) {
+            ct_stage<T, S, TW_HELD, LN, LG, LR>(buf, base, t, active, nullptr, w[I], unused);
+            ct_stages_held<T, S, LN, LG + LR, I + 1>(buf, base, t, active, w);
+        } else {
+            ct_stage<T, S, TW_HELD, LN, LG, LR>(buf, base, t, active, nullptr, unused, unused);
+            ct_stages_held<T, S, LN, LG + LR, I>(buf, base, t, active, w);
+        }
+    }
+}
+
+// Load the held twiddles of thread t for a length-n transform (16 <= n <= 4096).
+template <typename T>
+__device__ __forceinline__ void lds_fft_twiddles(int n, int t, const cpx<T>* __restrict__ twst, cpx<T> (&w)[2][15]) {
+    switch (ilog2(n)) {
+    case 4: ct_fetch_held<T, 4, 0, 0>(twst, t, w); break;
+    case 5: ct_fetch_held<T, 5, 0, 0>(twst, t, w); break;
+    case 6: ct_fetch_held<T, 6, 0, 0>(twst, t, w); break;
+    case 7: ct_fetch_held<T, 7, 0, 0>(twst, t, w); break;
+    case 8: ct_fetch_held<T, 8, 0, 0>(twst, t, w); break;
+    case 9: ct_fetch_held<T, 9, 0, 0>(twst, t, w); break;
+    case 10: ct_fetch_held<T, 10, 0, 0>(twst, t, w); break;
+    case 11: ct_fetch_held<T, 11, 0, 0>(twst, t, w); break;
+    default: ct_fetch_held<T, 12, 0, 0>(twst, t, w); break;
+    }
+}
+
+// In-place length-n FFT (16 <= n <= 4096) with the thread's twiddles held in
+// registers (from lds_fft_twiddles for the same n and t).
+template <typename T, int S>
+__device__ __forceinline__ void lds_fft_held(cpx<T>* buf, int base, int n, int t, bool active, cpx<T> (&w)[2][15]) {
+    switch (ilog2(n)) {
+    case 4: ct_stages_held<T, S, 4, 0, 0>(buf, base, t, active, w); break;
+    case 5: ct_stages_held<T, S, 5, 0, 0>(buf, base, t, active, w); break;
+    case 6: ct_stages_held<T, S, 6, 0, 0>(buf, base, t, active, w); break;
+    case 7: ct_stages_held<T, S, 7, 0, 0>(buf, base, t, active, w); break;
+    case 8: ct_stages_held<T, S, 8, 0, 0>(buf, base, t, active, w); break;
+    case 9: ct_stages_held<T, S, 9, 0, 0>(buf, base, t, active, w); break;
+    case 10: ct_stages_held<T, S, 10, 0, 0>(buf, base, t, active, w); break;
+    case 11: ct_stages_held<T, S, 11, 0, 0>(buf, base, t, active, w); break;
+    default: ct_stages_held<T, S, 12, 0, 0>(buf, base, t, active, w); break;
+    }
 }
 
 // In-place length-n FFT (16 <= n <= 8192, a power of two) of the sequence at
@@ -254,16 +324,16 @@ template <typename T, int S, bool LA = true>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int n, int t, bool active,
                                         const cpx<T>* __restrict__ twst) {
     switch (ilog2(n)) {
-    case 4: ct_fft<T, S, LA, 4>(buf, base, t, active, twst); break;
-    case 5: ct_fft<T, S, LA, 5>(buf, base, t, active, twst); break;
-    case 6: ct_fft<T, S, LA, 6>(buf, base, t, active, twst); break;
-    case 7: ct_fft<T, S, LA, 7>(buf, base, t, active, twst); break;
-    case 8: ct_fft<T, S, LA, 8>(buf, base, t, active, twst); break;
-    case 9: ct_fft<T, S, LA, 9>(buf, base, t, active, twst); break;
-    case 10: ct_fft<T, S, LA, 10>(buf, base, t, active, twst); break;
-    case 11: ct_fft<T, S, LA, 11>(buf, base, t, active, twst); break;
-    case 12: ct_fft<T, S, LA, 12>(buf, base, t, active, twst); break;
-    default: ct_fft<T, S, LA, 13>(buf, base, t, active, twst); break;
+    case 4: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 4>(buf, base, t, active, twst); break;
+    case 5: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 5>(buf, base, t, active, twst); break;
+    case 6: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 6>(buf, base, t, active, twst); break;
+    case 7: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 7>(buf, base, t, active, twst); break;
+    case 8: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 8>(buf, base, t, active, twst); break;
+    case 9: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 9>(buf, base, t, active, twst); break;
+    case 10: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 10>(buf, base, t, active, twst); break;
+    case 11: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 11>(buf, base, t, active, twst); break;
+    case 12: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 12>(buf, base, t, active, twst); break;
+    default: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 13>(buf, base, t, active, twst); break;
     }
 }
 

@@ -410,10 +410,8 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
 }
 
 // ------------------------------------------------------------------ y-pass
-// y-pass FFTs: twiddle look-ahead (more registers)
-constexpr bool Y_LOOKAHEAD = false;
 // persistent y-pass blocks load the next tile while working on the current one
-constexpr bool Y_PREFETCH = true;
+constexpr bool Y_PREFETCH = false;
 
 // Tile <-> LDS copies.  Element e = j * W + c of a tile (global order) sits
 // in LDS column c at logical c * n_y + j.  A thread moves the elements
@@ -491,8 +489,10 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // transform carry the factor 1/n_y of the pre-scaled tables.)
 // Column 0 holds the DC (.x) and tau-Nyquist (.y) modes in y-physical form in
 // every array; its DC is invariant and its Nyquist multipliers are scalars.
+// FP32 blocks of up to 512 threads are held to 128 VGPRs so that several
+// share a compute unit (as many as their LDS allows).
 template <typename T, int NT, int STAGE>
-__global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
+__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
                                                int n_items, cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
                                                cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
                                                const cpx<T>* __restrict__ tabs,
@@ -504,6 +504,11 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     // transformed and combined, so its memory latency is hidden.
     const cpx<T>* src = STAGE == 0 ? C : B;
     T vr[16], vi[16];
+    // Stockham twiddles of this thread's column transform, loaded once per
+    // transform length and held in registers for every tile (forward and
+    // inverse), so no tile waits on twiddle loads.
+    cpx<T> ytw[2][15];
+    int tw_ny = 0;
     int item = blockIdx.x;
     if (Y_PREFETCH && item < n_items) tile_fetch<T, NT>(descs, items[item], true, src, tid, vr, vi);
     for (; item < n_items; item += gridDim.x) {
@@ -528,6 +533,10 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
     // tile element e = j * W + c (global order) <-> LDS column c at logical c * Ny + j
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
+    if (Ny != tw_ny) {
+        lds_fft_twiddles<T>(Ny, ft, twst, ytw);
+        tw_ny = Ny;
+    }
     tile_put<T, NT>(lds, vr, vi, ne, tid, W, lw, Ny);
     __syncthreads();
     if (Y_PREFETCH) {
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
         tile_fetch<T, NT>(descs, items[more ? item + gridDim.x : item], more, src, tid, vr, vi);
     }
     if (STAGE == 0) {
-        lds_fft<T, -1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
+        lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
         #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + q * NT;
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
         continue;
     }
 
-    lds_fft<T, -1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
+    lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
     // indices n and Ny - n.  A thread has at most 9 half-tile items
     // (Nh * W <= 8 NT + W); their global loads are issued before use.
@@ -599,7 +608,7 @@ __global__ __launch_bounds__(NT) void y_kernel(const InstDesc* __restrict__ desc
         }
     }
     __syncthreads();
-    lds_fft<T, 1, Y_LOOKAHEAD>(lds, fc * Ny, Ny, ft, act, twst);
+    lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
     tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
 #undef KZK_LI
     if (col0) {
