@@ -890,7 +890,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
 // R~ = F_y^-1 conj(E) (Lh + Mh).  Column 0 (DC, tau-Nyquist) pointwise in y;
 // its Lh slot holds the raw column.
 template <typename T, int NT, int STAGE>
-__global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_adj_kernel(const InstDesc* __restrict__ descs,
                                                    const YItem* __restrict__ items, const cpx<T>* __restrict__ In,
                                                    cpx<T>* __restrict__ Lh, cpx<T>* __restrict__ Tout,
                                                    cpx<T>* __restrict__ Rout, const cpx<T>* __restrict__ tabs,
@@ -916,10 +916,18 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
     const int half = Ny >> 1;
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
 
+    // Stage 1 holds this thread's twiddles in registers for both of its
+    // transforms; stage 2 keeps 16 values per thread across its second
+    // transform and loads its twiddles per transform stage instead.
+    cpx<T> ytw[2][15];
+    if (STAGE == 1) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
     cpx<T> keep[16];
     tile_load<T, NT>(lds, It, ne, tid, W, lw, Ny, keep);
     __syncthreads();
-    lds_fft<T, -1>(lds, fc * Ny, Ny, ft, act, twst);
+    if (STAGE == 1)
+        lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
+    else
+        lds_fft<T, -1, false>(lds, fc * Ny, Ny, ft, act, twst);
     #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = tid + q * NT;
@@ -941,7 +949,10 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
+    if (STAGE == 1)
+        lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
+    else
+        lds_fft<T, 1, false>(lds, fc * Ny, Ny, ft, act, twst);
     tile_store<T, NT>(Tt, lds, ne, tid, W, lw, Ny, col0);
     if (STAGE == 2) {
         __syncthreads();
@@ -951,7 +962,7 @@ __global__ __launch_bounds__(NT) void y_adj_kernel(const InstDesc* __restrict__ 
             if (e < ne) lds[KZK_LI(e)] = keep[q];
         }
         __syncthreads();
-        lds_fft<T, 1>(lds, fc * Ny, Ny, ft, act, twst);
+        lds_fft<T, 1, false>(lds, fc * Ny, Ny, ft, act, twst);
         tile_store<T, NT>(Rout + to, lds, ne, tid, W, lw, Ny, col0);
     }
 #undef KZK_LI
