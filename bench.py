@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+PROFILE_EVERY = 8              # per-kernel HIP events on every 8th step of the timed marches
 ALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}   # vector FMA without packed FP32 (256 CU x 64 lanes x 2 x 2.4 GHz)
 
 WORKLOADS = {
@@ -201,7 +202,7 @@ def main():
         raise SystemExit("device status %d during warm-up" % st)
 
     if not args.no_profile:
-        plan.profile(True)
+        plan.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):

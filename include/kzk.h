@@ -143,10 +143,13 @@ enum {
     KZK_N_KINDS = 8
 };
 
-/* Bracket every later kernel launch of the plan with HIP events on its
- * stream (on = 1) or stop doing so (on = 0).  While on, graph replay is not
- * used.  For measurement; adds an event record per launch. */
-kzk_status kzk_profile_enable(kzk_plan *plan, int32_t on);
+/* Bracket later kernel launches of the plan with HIP events on its stream:
+ * every = 0 stops; every = k >= 1 brackets the launches of the forward steps
+ * s with s % k == 0 and all other launches (k = 1: every launch).  While on,
+ * graph replay is not used.  For measurement; an event record costs a few
+ * microseconds of queue time, so sampling (k > 1) keeps the march it
+ * measures close to an unprofiled one.  KZK_ERR_ARG for every < 0. */
+kzk_status kzk_profile_enable(kzk_plan *plan, int32_t every);
 
 /* Synchronise the stream and return, per kernel class k < n_kinds, the summed
  * event time ms[k] (milliseconds) and the number of launches count[k] since

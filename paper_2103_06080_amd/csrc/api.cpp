@@ -58,8 +58,11 @@ struct kzk_plan {
     const void* g_u = nullptr;
     int g_first = -1, g_n = -1;
 
-    // per-kernel timing with HIP events (kzk_profile_enable)
+    // per-kernel timing with HIP events (kzk_profile_enable): launches outside
+    // the step loop always, those of step s when s % prof_every == 0
     bool prof = false;
+    int prof_every = 1;
+    bool prof_now = false;
     struct Ev { int kind; hipEvent_t a, b; };
     std::vector<Ev> ev_used;
     std::vector<hipEvent_t> ev_pool;
@@ -107,7 +110,7 @@ struct ProfScope {
     int kind;
     hipEvent_t a = nullptr;
     ProfScope(kzk_plan* p_, int kind_) : p(p_), kind(kind_) {
-        if (p->prof && (a = take_event(p))) (void)hipEventRecord(a, p->stream);
+        if (p->prof && p->prof_now && (a = take_event(p))) (void)hipEventRecord(a, p->stream);
     }
     ~ProfScope() {
         if (!a) return;
@@ -217,6 +220,7 @@ hipError_t ypass(kzk_plan* p, int stage) {
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
 kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
     for (int s = first; s < first + n; ++s) {
+        p->prof_now = s % p->prof_every == 0;
         if (p->any_D_sched) {
             kzk_status st = build_tables(p, s, true);
             if (st != KZK_OK) return st;
@@ -226,6 +230,7 @@ kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
         if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s + 1) != hipSuccess) return KZK_ERR_DEVICE;
         if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
     }
+    p->prof_now = true;
     return KZK_OK;
 }
 
@@ -504,9 +509,11 @@ kzk_status kzk_step(kzk_plan* p, void* u, int32_t first, int32_t n) {
     return hipGraphLaunch(p->gexec, p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
 }
 
-kzk_status kzk_profile_enable(kzk_plan* p, int32_t on) {
-    if (!p) return KZK_ERR_ARG;
-    p->prof = on != 0;
+kzk_status kzk_profile_enable(kzk_plan* p, int32_t every) {
+    if (!p || every < 0) return KZK_ERR_ARG;
+    p->prof = every != 0;
+    p->prof_every = every > 0 ? every : 1;
+    p->prof_now = true;
     return KZK_OK;
 }
 

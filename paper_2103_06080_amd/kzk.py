@@ -213,8 +213,10 @@ class Plan:
                "kzk_adjoint")
         return g
 
-    def profile(self, on: bool):
-        _check(lib().kzk_profile_enable(self.h, 1 if on else 0), "kzk_profile_enable")
+    def profile(self, on: bool, every: int = 1):
+        """Per-kernel HIP-event timing of later launches (forward steps: every
+        `every`-th step); off with on=False."""
+        _check(lib().kzk_profile_enable(self.h, int(every) if on else 0), "kzk_profile_enable")
 
     def profile_read(self):
         """{kind: (total ms, launches)} since the last read (synchronises)."""

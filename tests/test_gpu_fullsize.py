@@ -185,3 +185,24 @@ def test_autotune_picks_a_supported_size_and_keeps_results(torch_cuda, orc, dtyp
     plan.step(u, 0, 10)
     assert plan.poll() == 0
     assert rel_l2(plan.unpack(u)[0], orc.run(p)) < TOL[dtype]
+
+
+def test_profile_sampling_counts_launches(torch_cuda):
+    """kzk_profile_enable(k): the launches of every k-th step are bracketed
+    (and the march's result does not depend on it)."""
+    from paper_2103_06080_amd import kzk
+    p = I.c1(n_steps=20)
+    p = I.Problem(**{**p.__dict__, "D_const": None, "nl_const": None})   # per-step tables
+    plan = kzk.Plan(p, dtype="f64")
+    ref = plan.pack([p.u0])
+    plan.step(ref, 0, 20)
+    for every, n_prof in ((1, 20), (4, 5), (7, 3)):
+        u = plan.pack([p.u0])
+        plan.profile(True, every=every)
+        plan.step(u, 0, 20)
+        prof = plan.profile_read()
+        plan.profile(False)
+        assert prof["tau_pass"][1] == 2 * n_prof and prof["y_pass1"][1] == n_prof, (every, prof)
+        assert prof["y_pass2"][1] == n_prof and prof["tables"][1] == n_prof, (every, prof)
+        assert torch_cuda.equal(u, ref)
+    assert plan.poll() == 0
