@@ -4,7 +4,7 @@
 One bench "step" is one pass of the whole hot path over one batch of
 synthetic input: the full inhomogeneous-medium march of an 8192 x 4096
 (tau x y) N-wave, 2000 ExpRK22 steps with x-dependent nl(x), D(x) and
-absorption, in FP32 (the FP64 multiplier tables rebuilt every step).
+absorption, in FP32 (the FP64 multipliers of each step evaluated in the first y-pass).
 Consecutive bench steps continue the march (steps k*2000 .. (k+1)*2000-1),
 so every timed step does identical work on a field resident in HBM.
 

@@ -208,27 +208,25 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
                                    Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->dStatus, p->stream);
 }
 
-hipError_t ypass(kzk_plan* p, int stage) {
+// step: the ExpRK22 step, for instances with a D schedule (the y-pass
+// computes their multipliers; the others read the tables built at create).
+hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB,
-                                    p->dP, p->dU, p->dTab, p->dTwSt, p->stream);
+                                    p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
     return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB, p->dP,
-                                 p->dU, p->dTab, p->dTwSt, p->stream);
+                                 p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
 kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
     for (int s = first; s < first + n; ++s) {
         p->prof_now = s % p->prof_every == 0;
-        if (p->any_D_sched) {
-            kzk_status st = build_tables(p, s, true);
-            if (st != KZK_OK) return st;
-        }
         if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
-        if (ypass(p, 1) != hipSuccess) return KZK_ERR_DEVICE;
+        if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
         if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s + 1) != hipSuccess) return KZK_ERR_DEVICE;
-        if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
+        if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
     }
     p->prof_now = true;
     return KZK_OK;
@@ -689,12 +687,11 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
             return KZK_ERR_DEVICE;
         // recompute the segment, storing u^n and u* in physical space
         for (int s = s0; s < s1; ++s) {
-            if (p->any_D_sched && (st = build_tables(p, s, true)) != KZK_OK) return st;
             if (tau(p, 3, nullptr, Un + (size_t)(s - s0) * ub, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
-            if (ypass(p, 1) != hipSuccess) return KZK_ERR_DEVICE;
+            if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
             if (tau(p, 3, nullptr, Us + (size_t)(s - s0) * ub, p->dC, p->dB, s + 1) != hipSuccess)
                 return KZK_ERR_DEVICE;
-            if (ypass(p, 2) != hipSuccess) return KZK_ERR_DEVICE;
+            if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
         }
         // adjoint steps back through the segment
         for (int s = s1 - 1; s >= s0; --s) {

@@ -409,6 +409,73 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
 }
 
+// ------------------------------------------------------------------ multiplier tables
+// phi-functions in FP64: Taylor series of phi2 (Horner) for |z| < 1, with
+// phi1 = 1 + z phi2 and e^z = 1 + z phi1; closed forms otherwise.
+// phi2 = sum_j z^j / (j+2)!; for |z| < 1 the terms beyond j = 17 add less
+// than 1/20! relative to phi2 ~ 1/2, far below the FP64 rounding unit.
+__host__ __device__ constexpr double inv_fact_plus2(int j) {
+    double f = 1.0;
+    for (int i = 2; i <= j + 2; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+__device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, cpx<double>& p2) {
+    const cpx<double> z = {zr, zi};
+    if (zr * zr + zi * zi < 1.0) {
+        constexpr int J = 17;
+        cpx<double> p = {inv_fact_plus2(J), 0.0};
+        #pragma unroll
+        for (int j = J - 1; j >= 0; --j) {
+            p = cmul(z, p);
+            p.x += inv_fact_plus2(j);
+        }
+        p2 = p;
+        p1 = cmul(z, p2);
+        p1.x += 1.0;
+        e = cmul(z, p1);
+        e.x += 1.0;
+        return;
+    }
+    double ex = exp(zr), sn, cs;
+    sincos(zi, &sn, &cs);
+    e = {ex * cs, ex * sn};
+    const double inv = 1.0 / (zr * zr + zi * zi);
+    cpx<double> em1 = {e.x - 1.0, e.y};
+    p1 = inv * cmulc(em1, z);                 // (e^z - 1) / z
+    cpx<double> p1m1 = {p1.x - 1.0, p1.y};
+    p2 = inv * cmulc(p1m1, z);                // (phi1 - 1) / z
+}
+
+// Multipliers of mode (m, n) for step `step` (tau-mode m >= 1, |ky index| n),
+// scaled by 1/n_y for the inverse y-transform: E/n_y, h Phi1/n_y, h Phi2/n_y.
+template <typename T>
+__device__ __forceinline__ void mode_multipliers(const InstDesc& d, int m, int n, int step, cpx<T>& E, cpx<T>& P1,
+                                                 cpx<T>& P2) {
+    const double h = d.h;
+    const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
+    const double kt = 2.0 * KZK_PI * (double)m / d.L_tau;
+    const double ky = 2.0 * KZK_PI * (double)n / d.L_y;
+    // z = h l,  l = i Dbar ky^2 / (2 kt) - A kt^2
+    cpx<double> e, p1, p2;
+    phis_f64(-h * d.A * kt * kt, h * Dbar * ky * ky / (2.0 * kt), e, p1, p2);
+    const double s = 1.0 / (double)d.n_y;
+    E = cpx<T>{(T)(e.x * s), (T)(e.y * s)};
+    P1 = cpx<T>{(T)(h * s * p1.x), (T)(h * s * p1.y)};
+    P2 = cpx<T>{(T)(h * s * p2.x), (T)(h * s * p2.y)};
+}
+
+// The tau-Nyquist scalars (absorption only, ky-independent, not scaled).
+template <typename T>
+__device__ __forceinline__ void nyquist_multipliers(const InstDesc& d, T& E, T& P1, T& P2) {
+    const double h = d.h;
+    const double kn = 2.0 * KZK_PI * (double)(-d.M) / d.L_tau;
+    cpx<double> e, p1, p2;
+    phis_f64(-h * d.A * kn * kn, 0.0, e, p1, p2);
+    E = (T)e.x;
+    P1 = (T)(h * p1.x);
+    P2 = (T)(h * p2.x);
+}
+
 // ------------------------------------------------------------------ y-pass
 // persistent y-pass blocks load the next tile while working on the current one
 constexpr bool Y_PREFETCH = false;
@@ -495,8 +562,8 @@ template <typename T, int NT, int STAGE>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
                                                int n_items, cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
                                                cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
-                                               const cpx<T>* __restrict__ tabs,
-                                               const cpx<T>* __restrict__ twst) {
+                                               cpx<T>* __restrict__ tabs,
+                                               const cpx<T>* __restrict__ twst, int step) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const int tid = threadIdx.x;
     // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...; the
@@ -528,10 +595,14 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     cpx<T>* Ut = U + to;
     const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
     const cpx<T>* tP1 = tE + d.tab_stride;
-    const cpx<T>* tP2 = tE + 2 * d.tab_stride;
+    cpx<T>* tP2 = tabs + d.off_tab + (long long)m0 * Nh + 2 * d.tab_stride;
     const bool col0 = (m0 == 0);
     // tile element e = j * W + c (global order) <-> LDS column c at logical c * Ny + j
 #define KZK_LI(e) padi((((e) & (W - 1)) * Ny) + ((e) >> lw))
+    // x-dependent D: stage 1 computes the multipliers of this step (FP64)
+    // instead of reading tables rebuilt every step, and stores h Phi2 / n_y
+    // into its table for stage 2
+    const bool otf = STAGE == 1 && d.D_step != nullptr;
 
     if (Ny != tw_ny) {
         lds_fft_twiddles<T>(Ny, ft, twst, ytw);
@@ -569,17 +640,20 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const int n = h >> lw, cc = h & (W - 1);
             const int j2 = (n == 0 || 2 * n == Ny) ? n : Ny - n;
             if (STAGE == 1) {
-                tb[q][0] = tE[h];
-                tb[q][1] = tP1[h];
-                tb[q][2] = tP2[h];
+                if (!otf) {
+                    tb[q][0] = tE[h];
+                    tb[q][1] = tP1[h];
+                    tb[q][2] = tP2[h];
+                }
                 ua[q][0] = Ut[n * W + cc];
                 ua[q][1] = Ut[j2 * W + cc];
             } else {
-                tb[q][2] = tP2[h];
+                if (!otf) tb[q][2] = tP2[h];
                 ua[q][0] = Pt[n * W + cc];
                 ua[q][1] = Pt[j2 * W + cc];
             }
         }
+
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int h = tid + (q0 + q) * NT;
@@ -587,6 +661,22 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const int n = h >> lw, cc = h & (W - 1);
             const bool keep_col = !(col0 && cc == 0);
             const bool two = !(n == 0 || 2 * n == Ny);
+            if (otf) {
+                // column 0 of the first tile is handled pointwise below (its
+                // combine values are never stored); its table slots hold the
+                // tau-Nyquist scalars (n = 0) and zeros, as the tables kernel's
+                if (m0 + cc > 0) {
+                    mode_multipliers<T>(d, m0 + cc, n, step, tb[q][0], tb[q][1], tb[q][2]);
+                } else {
+                    tb[q][0] = tb[q][1] = tb[q][2] = cpx<T>{(T)0, (T)0};
+                    if (n == 0) {
+                        T e, p1, p2;
+                        nyquist_multipliers<T>(d, e, p1, p2);
+                        tb[q][2] = cpx<T>{p2, (T)0};
+                    }
+                }
+                tP2[h] = tb[q][2];
+            }
             #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 if (pass == 1 && !two) break;
@@ -613,7 +703,14 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
 #undef KZK_LI
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
-        const T EN = tE[0].x, P1N = tP1[0].x, P2N = tP2[0].x;
+        T EN, P1N, P2N;
+        if (otf) {
+            nyquist_multipliers<T>(d, EN, P1N, P2N);
+        } else {
+            EN = tE[0].x;
+            P1N = tP1[0].x;
+            P2N = tP2[0].x;
+        }
         for (int y = tid; y < Ny; y += NT) {
             const long long o = (long long)y * W;
             const cpx<T> b = Bt[o];
@@ -983,43 +1080,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_a
     }
 }
 
-// ------------------------------------------------------------------ multiplier tables
-// phi-functions in FP64: Taylor series of phi2 (Horner) for |z| < 1, with
-// phi1 = 1 + z phi2 and e^z = 1 + z phi1; closed forms otherwise.
-// phi2 = sum_j z^j / (j+2)!; for |z| < 1 the terms beyond j = 17 add less
-// than 1/20! relative to phi2 ~ 1/2, far below the FP64 rounding unit.
-__host__ __device__ constexpr double inv_fact_plus2(int j) {
-    double f = 1.0;
-    for (int i = 2; i <= j + 2; ++i) f *= (double)i;
-    return 1.0 / f;
-}
-__device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, cpx<double>& p2) {
-    const cpx<double> z = {zr, zi};
-    if (zr * zr + zi * zi < 1.0) {
-        constexpr int J = 17;
-        cpx<double> p = {inv_fact_plus2(J), 0.0};
-        #pragma unroll
-        for (int j = J - 1; j >= 0; --j) {
-            p = cmul(z, p);
-            p.x += inv_fact_plus2(j);
-        }
-        p2 = p;
-        p1 = cmul(z, p2);
-        p1.x += 1.0;
-        e = cmul(z, p1);
-        e.x += 1.0;
-        return;
-    }
-    double ex = exp(zr), sn, cs;
-    sincos(zi, &sn, &cs);
-    e = {ex * cs, ex * sn};
-    const double inv = 1.0 / (zr * zr + zi * zi);
-    cpx<double> em1 = {e.x - 1.0, e.y};
-    p1 = inv * cmulc(em1, z);                 // (e^z - 1) / z
-    cpx<double> p1m1 = {p1.x - 1.0, p1.y};
-    p2 = inv * cmulc(p1m1, z);                // (phi1 - 1) / z
-}
-
+// ------------------------------------------------------------------ multiplier tables (kernel)
 template <typename T>
 __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict__ descs, int inst,
                                                      cpx<T>* __restrict__ tabs, int step) {
@@ -1034,29 +1095,19 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
     cpx<T>* tE = tabs + d.off_tab + o;
     cpx<T>* tP1 = tE + d.tab_stride;
     cpx<T>* tP2 = tE + 2 * d.tab_stride;
-    const double h = d.h;
-    cpx<double> e, p1, p2;
     if (m == 0) {
         if (n == 0) {   // tau-Nyquist scalars (absorption only), not scaled
-            const double kn = 2.0 * KZK_PI * (double)(-d.M) / d.L_tau;
-            phis_f64(-h * d.A * kn * kn, 0.0, e, p1, p2);
-            *tE = cpx<T>{(T)e.x, (T)0};
-            *tP1 = cpx<T>{(T)(h * p1.x), (T)0};
-            *tP2 = cpx<T>{(T)(h * p2.x), (T)0};
+            T e, p1, p2;
+            nyquist_multipliers<T>(d, e, p1, p2);
+            *tE = cpx<T>{e, (T)0};
+            *tP1 = cpx<T>{p1, (T)0};
+            *tP2 = cpx<T>{p2, (T)0};
         } else {
             *tE = *tP1 = *tP2 = cpx<T>{(T)0, (T)0};
         }
         return;
     }
-    const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
-    const double kt = 2.0 * KZK_PI * (double)m / d.L_tau;
-    const double ky = 2.0 * KZK_PI * (double)n / d.L_y;
-    // z = h l,  l = i Dbar ky^2 / (2 kt) - A kt^2
-    phis_f64(-h * d.A * kt * kt, h * Dbar * ky * ky / (2.0 * kt), e, p1, p2);
-    const double s = 1.0 / (double)d.n_y;
-    *tE = cpx<T>{(T)(e.x * s), (T)(e.y * s)};
-    *tP1 = cpx<T>{(T)(h * s * p1.x), (T)(h * s * p1.y)};
-    *tP2 = cpx<T>{(T)(h * s * p2.x), (T)(h * s * p2.y)};
+    mode_multipliers<T>(d, m, n, step, *tE, *tP1, *tP2);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1083,21 +1134,21 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 
 template <typename T, int NT>
 static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                              void* C, const void* B, void* P, void* U, const void* tabs, const void* twst,
+                              void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
                               hipStream_t s) {
     dim3 g(max_blocks > 0 && max_blocks < n_items ? max_blocks : n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
     cpx<T>* p = static_cast<cpx<T>*>(P);
     cpx<T>* u = static_cast<cpx<T>*>(U);
-    const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
+    cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     return hipGetLastError();
 }
 
@@ -1132,14 +1183,16 @@ bool y_threads_supported(int is_f64, int nt) {
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                    void* C, const void* B, void* P, void* U, const void* tabs, const void* twst, hipStream_t s) {
+                    void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
+                    hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (nt) {
-    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
-    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
+    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
+    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, s);
+            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step,
+                                        s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -1229,7 +1282,7 @@ void stage_twiddles(double* out) {
     template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
                                       const void*, const void*, int, int, int, unsigned*, hipStream_t);              \
     template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, int, void*, const void*, void*,   \
-                                    void*, const void*, const void*, hipStream_t);                                   \
+                                    void*, void*, const void*, int, hipStream_t);                                    \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
