@@ -162,3 +162,30 @@ def test_multiplier_tables_match_oracle(torch_cuda, orc, dtype, h, A):
     assert abs(P2[0, 0] / h - orc.phi(2, zN)[0]) < tol
     if h == 0.5:
         assert np.abs(z).max() > 2.0 and np.abs(z[1:]).min() < 1.0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_stage1_phi2_of_a_scheduled_step_matches_oracle(torch_cuda, orc, dtype):
+    """With an x-dependent D the first y-pass evaluates the step's multipliers
+    itself and leaves h Phi2 / n_y in the table for the second; after a march
+    of k steps that table holds Phi2 of step k-1's D (|z| up to ~1.9)."""
+    from paper_2103_06080_amd import kzk
+    nt, ny, k = 64, 64, 5
+    p = small(nt, ny, n_steps=8, h=0.5, A=2e-3)
+    p.D_step = 0.05 * (1 + 0.3 * np.sin(np.arange(p.n_steps)))
+    p = I.Problem(**{**p.__dict__, "D_const": None, "nl_const": None})
+    plan = kzk.Plan(p, dtype=dtype)
+    u = plan.pack([p.u0 * 1e-3])
+    plan.step(u, 0, k)
+    assert plan.poll() == 0
+    _, _, P2 = plan.read_tables()
+    M, Nh = nt // 2, ny // 2 + 1
+    Db = float(p.D_step[k - 1])
+    z = np.array([[p.h * orc.symbol(p, m, n, Db) for n in range(Nh)] for m in range(M)])
+    r2 = orc.phi(2, z.ravel()).reshape(z.shape)
+    tol = 1e-14 if dtype == "f64" else 3e-7
+    assert np.abs(P2[1:] * ny / p.h - r2[1:]).max() < tol
+    zN = p.h * orc.symbol(p, M, 0, Db)
+    assert abs(P2[0, 0] / p.h - orc.phi(2, zN)[0]) < tol
+    assert np.abs(P2[0, 1:]).max() == 0
+    assert np.abs(z).max() > 1.5    # both branches of the phi evaluation are used
