@@ -631,6 +631,59 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // (Nh * W <= 8 NT + W); their global loads are issued before use.
     const int nh = Nh * W;
     constexpr int QH = 9;
+    if (STAGE == 1 && otf) {
+        // one item at a time (the FP64 multiplier code needs the registers);
+        // the U loads of the next item are in flight during this item's
+        // multipliers.  Column 0 of the first tile is handled pointwise below
+        // (its combine values are never stored); its table slots hold the
+        // tau-Nyquist scalars (n = 0) and zeros, as the tables kernel's.
+        cpx<T> u0, u1;
+        {
+            const int h = min(tid, nh - 1);
+            const int n = h >> lw, cc = h & (W - 1);
+            const int j2 = (n == 0 || 2 * n == Ny) ? n : Ny - n;
+            u0 = Ut[n * W + cc];
+            u1 = Ut[j2 * W + cc];
+        }
+        #pragma unroll
+        for (int q = 0; q < QH; ++q) {
+            cpx<T> x0 = u0, x1 = u1;
+            if (q + 1 < QH) {
+                const int hn = min(tid + (q + 1) * NT, nh - 1);
+                const int n = hn >> lw, cc = hn & (W - 1);
+                const int j2 = (n == 0 || 2 * n == Ny) ? n : Ny - n;
+                x0 = Ut[n * W + cc];
+                x1 = Ut[j2 * W + cc];
+            }
+            const int h = tid + q * NT;
+            if (h < nh) {
+                const int n = h >> lw, cc = h & (W - 1);
+                const bool keep_col = !(col0 && cc == 0);
+                const bool two = !(n == 0 || 2 * n == Ny);
+                cpx<T> E = {(T)0, (T)0}, P1 = E, P2 = E;
+                if (m0 + cc > 0) {
+                    mode_multipliers<T>(d, m0 + cc, n, step, E, P1, P2);
+                } else if (n == 0) {
+                    T e, p1, p2;
+                    nyquist_multipliers<T>(d, e, p1, p2);
+                    P2 = cpx<T>{p2, (T)0};
+                }
+                tP2[h] = P2;
+                #pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+                    if (pass == 1 && !two) break;
+                    const int j = pass ? Ny - n : n;
+                    const int e = j * W + cc, li = padi(cc * Ny + j);
+                    const cpx<T> bh = lds[li];
+                    const cpx<T> EU = cmul(E, pass ? u1 : u0);
+                    if (keep_col) Pt[e] = EU + cmul(P1 - P2, bh);
+                    lds[li] = EU + cmul(P1, bh);
+                }
+            }
+            u0 = x0;
+            u1 = x1;
+        }
+    } else {
     #pragma unroll
     for (int q0 = 0; q0 < QH; q0 += 3) {
         cpx<T> tb[3][3], ua[3][2];
@@ -640,15 +693,13 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const int n = h >> lw, cc = h & (W - 1);
             const int j2 = (n == 0 || 2 * n == Ny) ? n : Ny - n;
             if (STAGE == 1) {
-                if (!otf) {
-                    tb[q][0] = tE[h];
-                    tb[q][1] = tP1[h];
-                    tb[q][2] = tP2[h];
-                }
+                tb[q][0] = tE[h];
+                tb[q][1] = tP1[h];
+                tb[q][2] = tP2[h];
                 ua[q][0] = Ut[n * W + cc];
                 ua[q][1] = Ut[j2 * W + cc];
             } else {
-                if (!otf) tb[q][2] = tP2[h];
+                tb[q][2] = tP2[h];
                 ua[q][0] = Pt[n * W + cc];
                 ua[q][1] = Pt[j2 * W + cc];
             }
@@ -661,22 +712,6 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const int n = h >> lw, cc = h & (W - 1);
             const bool keep_col = !(col0 && cc == 0);
             const bool two = !(n == 0 || 2 * n == Ny);
-            if (otf) {
-                // column 0 of the first tile is handled pointwise below (its
-                // combine values are never stored); its table slots hold the
-                // tau-Nyquist scalars (n = 0) and zeros, as the tables kernel's
-                if (m0 + cc > 0) {
-                    mode_multipliers<T>(d, m0 + cc, n, step, tb[q][0], tb[q][1], tb[q][2]);
-                } else {
-                    tb[q][0] = tb[q][1] = tb[q][2] = cpx<T>{(T)0, (T)0};
-                    if (n == 0) {
-                        T e, p1, p2;
-                        nyquist_multipliers<T>(d, e, p1, p2);
-                        tb[q][2] = cpx<T>{p2, (T)0};
-                    }
-                }
-                tP2[h] = tb[q][2];
-            }
             #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
                 if (pass == 1 && !two) break;
@@ -696,6 +731,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 }
             }
         }
+    }
     }
     __syncthreads();
     lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
