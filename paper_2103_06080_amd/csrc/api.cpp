@@ -669,10 +669,28 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
     char* Un = (char*)p->dUn;
     char* Us = (char*)p->dUs;
 
-    // forward sweep, keeping the spectral state at the start of every segment
+    // Steps s0 .. s1-1 storing u^n and u* in physical space (stage inputs of
+    // the nonlinear term, needed by its Jacobians).
+    auto stored_steps = [&](int s0, int s1) -> kzk_status {
+        for (int s = s0; s < s1; ++s) {
+            if (tau(p, 3, nullptr, Un + (size_t)(s - s0) * ub, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
+            if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
+            if (tau(p, 3, nullptr, Us + (size_t)(s - s0) * ub, p->dC, p->dB, s + 1) != hipSuccess)
+                return KZK_ERR_DEVICE;
+            if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
+        }
+        return KZK_OK;
+    };
+    // forward sweep, keeping the spectral state at the start of every segment;
+    // the last segment stores its stage inputs right away (it is the first one
+    // the backward sweep needs, so it is not recomputed)
     if ((st = enqueue_forward(p, u0)) != KZK_OK) return st;
     for (int g = 0; g < nseg; ++g) {
         const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
+        if (g == nseg - 1) {
+            if ((st = stored_steps(s0, s1)) != KZK_OK) return st;
+            break;
+        }
         if (hipMemcpyAsync(ck + (size_t)(2 * g) * sb, p->dU, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess ||
             hipMemcpyAsync(ck + (size_t)(2 * g + 1) * sb, p->dC, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
             return KZK_ERR_DEVICE;
@@ -682,16 +700,13 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
     if (tau(p, 0, lam, nullptr, nullptr, p->dL, 0) != hipSuccess) return KZK_ERR_DEVICE;
     for (int g = nseg - 1; g >= 0; --g) {
         const int s0 = first + g * K, s1 = std::min(s0 + K, first + n);
-        if (hipMemcpyAsync(p->dU, ck + (size_t)(2 * g) * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess ||
-            hipMemcpyAsync(p->dC, ck + (size_t)(2 * g + 1) * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
-            return KZK_ERR_DEVICE;
-        // recompute the segment, storing u^n and u* in physical space
-        for (int s = s0; s < s1; ++s) {
-            if (tau(p, 3, nullptr, Un + (size_t)(s - s0) * ub, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
-            if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
-            if (tau(p, 3, nullptr, Us + (size_t)(s - s0) * ub, p->dC, p->dB, s + 1) != hipSuccess)
+        if (g < nseg - 1) {
+            if (hipMemcpyAsync(p->dU, ck + (size_t)(2 * g) * sb, sb, hipMemcpyDeviceToDevice, p->stream) != hipSuccess ||
+                hipMemcpyAsync(p->dC, ck + (size_t)(2 * g + 1) * sb, sb, hipMemcpyDeviceToDevice, p->stream) !=
+                    hipSuccess)
                 return KZK_ERR_DEVICE;
-            if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
+            // recompute the segment, storing u^n and u*
+            if ((st = stored_steps(s0, s1)) != KZK_OK) return st;
         }
         // adjoint steps back through the segment
         for (int s = s1 - 1; s >= s0; --s) {
