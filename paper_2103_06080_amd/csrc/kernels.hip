@@ -477,9 +477,6 @@ __device__ __forceinline__ void nyquist_multipliers(const InstDesc& d, T& E, T& 
 }
 
 // ------------------------------------------------------------------ y-pass
-// persistent y-pass blocks load the next tile while working on the current one
-constexpr bool Y_PREFETCH = false;
-
 // Tile <-> LDS copies.  Element e = j * W + c of a tile (global order) sits
 // in LDS column c at logical c * n_y + j.  A thread moves the elements
 // e = tid + q * NT (q < 16; a tile holds at most 16 NT elements) and issues
@@ -499,16 +496,12 @@ __device__ __forceinline__ void tile_load(cpx<T>* lds, const cpx<T>* __restrict_
     }
 }
 
-// The loads of a tile alone (into registers, consumed later by tile_put);
-// real and imaginary parts in separate arrays.
-// With live = false every load reads the tile's first element (the loads stay
-// unconditional, so no register copies wait for them).
+// The same in two steps, the loads into registers (real and imaginary parts
+// in separate arrays, which the compiler keeps in registers also in FP64
+// inside the persistent loop) and their LDS writes.
 template <typename T, int NT>
-__device__ __forceinline__ void tile_fetch(const InstDesc* __restrict__ descs, const YItem it, bool live,
-                                           const cpx<T>* __restrict__ src, int tid, T (&vr)[16], T (&vi)[16]) {
-    const InstDesc& d = descs[it.inst];
-    const int ne = live ? d.W * d.n_y : 1;
-    const cpx<T>* g = src + d.off_state + (long long)it.m0 * d.n_y;
+__device__ __forceinline__ void tile_fetch(const cpx<T>* __restrict__ g, int ne, int tid, T (&vr)[16],
+                                           T (&vi)[16]) {
     #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const cpx<T> x = g[min(tid + q * NT, ne - 1)];
@@ -559,16 +552,13 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // FP32 blocks of up to 512 threads are held to 128 VGPRs so that several
 // share a compute unit (as many as their LDS allows).
 template <typename T, int NT, int STAGE>
-__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(const InstDesc* __restrict__ descs, const YItem* __restrict__ items,
-                                               int n_items, cpx<T>* __restrict__ C, const cpx<T>* __restrict__ B,
-                                               cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
-                                               cpx<T>* __restrict__ tabs,
-                                               const cpx<T>* __restrict__ twst, int step) {
+__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
+        const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
+        const cpx<T>* __restrict__ B, cpx<T>* __restrict__ P, cpx<T>* __restrict__ U, cpx<T>* __restrict__ tabs,
+        const cpx<T>* __restrict__ twst, int step) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
     const int tid = threadIdx.x;
-    // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...; the
-    // input tile of the next one is loaded into registers while this one is
-    // transformed and combined, so its memory latency is hidden.
+    // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...
     const cpx<T>* src = STAGE == 0 ? C : B;
     T vr[16], vi[16];
     // Stockham twiddles of this thread's column transform, loaded once per
@@ -576,10 +566,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // inverse), so no tile waits on twiddle loads.
     cpx<T> ytw[2][15];
     int tw_ny = 0;
-    int item = blockIdx.x;
-    if (Y_PREFETCH && item < n_items) tile_fetch<T, NT>(descs, items[item], true, src, tid, vr, vi);
-    for (; item < n_items; item += gridDim.x) {
-    if (!Y_PREFETCH) tile_fetch<T, NT>(descs, items[item], true, src, tid, vr, vi);
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const YItem it = items[item];
     const InstDesc& d = descs[it.inst];
     const int Ny = d.n_y, W = d.W, lw = d.log2W, Nh = d.Nh;
@@ -604,16 +591,13 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // into its table for stage 2
     const bool otf = STAGE == 1 && d.D_step != nullptr;
 
+    tile_fetch<T, NT>(src + to, ne, tid, vr, vi);
     if (Ny != tw_ny) {
         lds_fft_twiddles<T>(Ny, ft, twst, ytw);
         tw_ny = Ny;
     }
     tile_put<T, NT>(lds, vr, vi, ne, tid, W, lw, Ny);
     __syncthreads();
-    if (Y_PREFETCH) {
-        const bool more = item + (int)gridDim.x < n_items;
-        tile_fetch<T, NT>(descs, items[more ? item + gridDim.x : item], more, src, tid, vr, vi);
-    }
     if (STAGE == 0) {
         lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
         #pragma unroll
