@@ -419,6 +419,23 @@ __host__ __device__ constexpr double inv_fact_plus2(int j) {
     for (int i = 2; i <= j + 2; ++i) f *= (double)i;
     return 1.0 / f;
 }
+// Closed forms (|z| >= 1).  Not inlined: the exponential and sine/cosine
+// need many registers, and keeping them out of line keeps them out of the
+// register allocation of the kernels that evaluate multipliers per mode
+// (|z| >= 1 holds for few modes).
+__device__ __attribute__((noinline)) void phis_closed_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1,
+                                                          cpx<double>& p2) {
+    const cpx<double> z = {zr, zi};
+    double ex = exp(zr), sn, cs;
+    sincos(zi, &sn, &cs);
+    e = {ex * cs, ex * sn};
+    const double inv = 1.0 / (zr * zr + zi * zi);
+    cpx<double> em1 = {e.x - 1.0, e.y};
+    p1 = inv * cmulc(em1, z);                 // (e^z - 1) / z
+    cpx<double> p1m1 = {p1.x - 1.0, p1.y};
+    p2 = inv * cmulc(p1m1, z);                // (phi1 - 1) / z
+}
+
 __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, cpx<double>& p2) {
     const cpx<double> z = {zr, zi};
     if (zr * zr + zi * zi < 1.0) {
@@ -436,14 +453,7 @@ __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, 
         e.x += 1.0;
         return;
     }
-    double ex = exp(zr), sn, cs;
-    sincos(zi, &sn, &cs);
-    e = {ex * cs, ex * sn};
-    const double inv = 1.0 / (zr * zr + zi * zi);
-    cpx<double> em1 = {e.x - 1.0, e.y};
-    p1 = inv * cmulc(em1, z);                 // (e^z - 1) / z
-    cpx<double> p1m1 = {p1.x - 1.0, p1.y};
-    p2 = inv * cmulc(p1m1, z);                // (phi1 - 1) / z
+    phis_closed_f64(zr, zi, e, p1, p2);
 }
 
 // Multipliers of mode (m, n) for step `step` (tau-mode m >= 1, |ky index| n),
