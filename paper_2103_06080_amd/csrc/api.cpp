@@ -40,6 +40,7 @@ struct kzk_plan {
     int ntw = 0, log2_ntw = 0;
     int y_threads = 0;
     int y_grid = 0;                       // persistent y-pass blocks (resident at once)
+    int tau_prog = 0;                     // every instance has M/16 >= W (tau-pass pair indexing)
     bool any_D_sched = false;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
@@ -171,6 +172,9 @@ kzk_status layout(kzk_plan* p) {
     if ((int)tau.size() > p->max_tau_items) return KZK_ERR_STATE;
     p->n_tau_items = (int)tau.size();
     p->n_y_items = (int)ys.size();
+    p->tau_prog = 1;
+    for (const InstDesc& d : p->desc)
+        if (d.M / 16 < d.W) p->tau_prog = 0;
     p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->device);
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
@@ -203,9 +207,11 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
     ProfScope ps(p, mode == 2 ? KZK_KIND_TAU : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
         return kzk::launch_tau<float>(mode, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in, (float*)u_out,
-                                      Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->dStatus, p->stream);
+                                      Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->tau_prog, p->dStatus,
+                                      p->stream);
     return kzk::launch_tau<double>(mode, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in, (double*)u_out,
-                                   Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->dStatus, p->stream);
+                                   Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->tau_prog, p->dStatus,
+                                   p->stream);
 }
 
 // step: the ExpRK22 step, for instances with a D schedule (the y-pass

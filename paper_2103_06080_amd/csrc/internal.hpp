@@ -38,10 +38,12 @@ struct YItem { int inst, m0; };
 // Launchers (kernels.hip).  All enqueue on `s` and return hipSuccess or the
 // launch error.  tw: twiddles exp(-2 pi i k / 2^log2_ntw); twst: per-stage
 // Stockham twiddles of all transform lengths 2^4 .. 2^13 (fft.hpp).
+// prog: every instance has M/16 >= W (tiled spectra; enables progression
+// indexing in the mode-2 kernel).
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, unsigned* status, hipStream_t s);
+                      int node, int tiled, int prog, unsigned* status, hipStream_t s);
 
 // y-pass over n_items column tiles with at most max_blocks persistent blocks
 // (0: one block per tile).  step: index into the D schedule of instances

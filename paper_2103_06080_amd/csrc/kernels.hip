@@ -208,20 +208,56 @@ __device__ __forceinline__ SpecIdx spec_idx(int log2W, int n_y, bool tiled) {
     return tiled ? SpecIdx{log2W, (1u << log2W) - 1u, (unsigned)n_y << log2W} : SpecIdx{30, (1u << 30) - 1u, 0u};
 }
 
-template <typename T>
+// Positions of the pair (k, M - k), k = min(t + q*tpr, M/2), in a spectral
+// row: X index of k, of (M - k) mod M, and twiddle index k << sh.  PROG: the
+// row is tiled and tpr (= M/16) is a multiple of the tile width, so k moves
+// by whole tiles from one q to the next and the positions are arithmetic
+// progressions in q (q < 8; q = 8 is k = M/2, used by t = 0 only).
+template <bool PROG>
+struct PairIdx {
+    unsigned k0, m0, w0, step, wstep, kh, wh;
+    int t, tpr, M, sh;
+    SpecIdx ix;
+    __device__ __forceinline__ PairIdx(SpecIdx ix_, int M_, int t_, int tpr_, int sh_)
+        : t(t_), tpr(tpr_), M(M_), sh(sh_), ix(ix_) {
+        if constexpr (PROG) {
+            step = __umul24((unsigned)tpr >> ix.lw, ix.stride);
+            k0 = ix(t);
+            m0 = ix(M - t);                       // ix(M) (t = 0) is only a base for q >= 1
+            w0 = (unsigned)t << sh;
+            wstep = (unsigned)tpr << sh;
+            kh = ix(M >> 1);
+            wh = (unsigned)(M >> 1) << sh;
+        }
+    }
+    __device__ __forceinline__ unsigned xk(int q) const {
+        if constexpr (PROG) return q < 8 ? k0 + q * step : kh;
+        else return ix(min(t + q * tpr, M >> 1));
+    }
+    __device__ __forceinline__ unsigned xm(int q) const {
+        if constexpr (PROG) return q == 0 ? (t == 0 ? k0 : m0) : q < 8 ? m0 - q * step : kh;
+        else return ix((M - min(t + q * tpr, M >> 1)) & (M - 1));
+    }
+    __device__ __forceinline__ unsigned w(int q) const {
+        if constexpr (PROG) return q < 8 ? w0 + q * wstep : wh;
+        else return (unsigned)min(t + q * tpr, M >> 1) << sh;
+    }
+};
+
+template <typename T, bool PROG = false>
 __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int M, int t,
                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
     // pairs k = t + q*tpr <= M/2, q < 9 (tpr = M/16); all loads of the thread are
     // issued before any is used, so their latencies overlap
     const int sh = log2_ntw - ilog2(2 * M);
     constexpr int Q = 9;
+    const PairIdx<PROG> pi(ix, M, t, tpr, sh);
     cpx<T> xk[Q], xm[Q], wv[Q];
     #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int k = min(t + q * tpr, M >> 1);
-        xk[q] = X[ix(k)];
-        xm[q] = X[ix((M - k) & (M - 1))];
-        wv[q] = tw[(unsigned)k << sh];
+        xk[q] = X[pi.xk(q)];
+        xm[q] = X[pi.xm(q)];
+        wv[q] = tw[pi.w(q)];
     }
     #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -240,10 +276,11 @@ __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix
     }
 }
 
-template <typename T>
+template <typename T, bool PROG = false>
 __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int M, int t,
                                          int tpr, const cpx<T>* __restrict__ tw, int log2_ntw) {
     const int sh = log2_ntw - ilog2(2 * M);
+    const PairIdx<PROG> pi(ix, M, t, tpr, sh);
     #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int k = t + q * tpr;
@@ -252,19 +289,21 @@ __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __
         const cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
         const cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
         const cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
-        const cpx<T> Q = mul_si<1>(cmul(tw[(unsigned)k << sh], D));    // i e^{-2 pi i k/N} D
+        const cpx<T> Q = mul_si<1>(cmul(tw[pi.w(q)], D));    // i e^{-2 pi i k/N} D
         if (k == 0) {
             X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
             continue;
         }
-        X[ix(k)] = A - Q;
-        if (2 * k != M) X[ix(M - k)] = conj(A + Q);
+        X[pi.xk(q)] = A - Q;
+        if (2 * k != M) X[pi.xm(q)] = conj(A + Q);
     }
 }
 
 // MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B (b via WENO5).
 // MODE 3: as MODE 2, and also stores the physical line u (for the adjoint).
-template <typename T, int MODE>
+// PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width in
+// every instance (progression indexing of the pre/post-processing pairs).
+template <typename T, int MODE, bool PROG = false>
 __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __restrict__ descs,
                                                           const TauItem* __restrict__ items,
                                                           const T* __restrict__ u_in, T* __restrict__ u_out,
@@ -306,12 +345,12 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
         lds_fft<T, -1>(lds, base, M, t, active, twst);
-        if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+        if (active) r2c_post<T, PROG>(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
         return;
     }
 
     // inverse tau-transform of C~ into the line buffer
-    if (active) c2r_pre(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    if (active) c2r_pre<T, PROG>(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
     __syncthreads();
     lds_fft<T, 1>(lds, base, M, t, active, twst);
 
@@ -406,7 +445,7 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     }
     __syncthreads();
     lds_fft<T, -1>(lds, base, M, t, active, twst);
-    if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+    if (active) r2c_post<T, PROG>(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
 }
 
 // ------------------------------------------------------------------ multiplier tables
@@ -1145,7 +1184,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, unsigned* status, hipStream_t s) {
+                      int node, int tiled, int prog, unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     dim3 g(n_items), b(TAU_THREADS);
     const cpx<T>* ci = static_cast<const cpx<T>*>(Cin);
@@ -1155,7 +1194,14 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
     switch (mode) {
     case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
-    case 2: hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 2:
+        if (prog && tiled)
+            hipLaunchKernelGGL((tau_kernel<T, 2, true>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws,
+                               log2_ntw, node, tiled, status);
+        else
+            hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws,
+                               log2_ntw, node, tiled, status);
+        break;
     case 3: hipLaunchKernelGGL((tau_kernel<T, 3>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
@@ -1310,7 +1356,7 @@ void stage_twiddles(double* out) {
 
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
-                                      const void*, const void*, int, int, int, unsigned*, hipStream_t);              \
+                                      const void*, const void*, int, int, int, int, unsigned*, hipStream_t);         \
     template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, int, void*, const void*, void*,   \
                                     void*, void*, const void*, int, hipStream_t);                                    \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
