@@ -40,7 +40,7 @@ struct kzk_plan {
     int ntw = 0, log2_ntw = 0;
     int y_threads = 0;
     int y_grid = 0;                       // persistent y-pass blocks (resident at once)
-    int tau_prog = 0;                     // every instance has M/16 >= W (tau-pass pair indexing)
+    int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
     bool any_D_sched = false;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
@@ -174,7 +174,7 @@ kzk_status layout(kzk_plan* p) {
     p->n_y_items = (int)ys.size();
     p->tau_prog = 1;
     for (const InstDesc& d : p->desc)
-        if (d.M / 16 < d.W) p->tau_prog = 0;
+        if (d.M / 16 < d.W || d.M < 256) p->tau_prog = 0;
     p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->device);
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||

@@ -38,8 +38,8 @@ struct YItem { int inst, m0; };
 // Launchers (kernels.hip).  All enqueue on `s` and return hipSuccess or the
 // launch error.  tw: twiddles exp(-2 pi i k / 2^log2_ntw); twst: per-stage
 // Stockham twiddles of all transform lengths 2^4 .. 2^13 (fft.hpp).
-// prog: every instance has M/16 >= W (tiled spectra; enables progression
-// indexing in the mode-2 kernel).
+// prog: every instance has M/16 >= W and M >= 256 (tiled spectra; enables
+// progression indexing in the mode-2 kernel).
 template <typename T>
 hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
@@ -72,7 +72,7 @@ hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* 
 // Number of complex entries of the per-stage twiddle table (all lengths).
 int stage_twiddle_entries();
 // Fill it (FP64) in the layout of fft.hpp: for each length 2^LN (LN = 4..13),
-// for each stage with Ns > 1, entries exp(-2 pi i k s / (Ns R)) at k*R + s.
+// for each stage with Ns > 1, entries exp(-2 pi i k s / (Ns R)) at s*Ns + k.
 void stage_twiddles(double* out_interleaved);
 
 // Block sizes of the y-pass for which kernels are compiled.

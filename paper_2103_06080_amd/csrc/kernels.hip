@@ -53,6 +53,34 @@ template <> __device__ __forceinline__ double rcp<double>(double x) {
 }
 
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+// maximum that propagates NaN (IEEE 754-2019 maximum; v_maximum3_f32 in FP32)
+template <typename T> __device__ __forceinline__ T nmax(T a, T b) { return __builtin_elementwise_maximum(a, b); }
+
+// Raw buffer access (gfx9 descriptor: 32-bit data format, no stride, no
+// range limit below 2 GiB): a per-thread byte offset plus a wave-uniform byte
+// offset, so that accesses at uniform strides need no per-access address
+// arithmetic.  Every caller stays inside the array it addresses.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, cpx<T> v) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff, 0);
+    }
+}
 template <typename T> __device__ __forceinline__ bool finite_val(T x);
 template <> __device__ __forceinline__ bool finite_val<float>(float x) { return fabsf(x) <= FLT_MAX; }
 template <> __device__ __forceinline__ bool finite_val<double>(double x) { return fabs(x) <= DBL_MAX; }
@@ -88,10 +116,12 @@ __device__ __forceinline__ T weno_face(T v0, T v1, T v2, T v3, T v4, T eps) {
 // and second differences D_j = d_j - d_{j-1} of the split flux,
 //   beta_r = 13/12 D^2 + 1/4 b_r^2 with b_r = D +- 2 d or d_{j-1} + d_j,
 //   q_0 - q_1 = (D_{j-1} - D_j)/3,  q_2 - q_1 = (D_j - D_{j+1})/6,
-// and the face value is q_1 + w_0 (q_0 - q_1) + w_2 (q_2 - q_1).
+// and the face value is q_1 + w_0 (q_0 - q_1) + w_2 (q_2 - q_1).  The code
+// carries 4 (eps + beta_r) = 13/3 D^2 + b_r^2 + 4 eps, a power-of-two scaling
+// common to the three weights (exact; the weights are unchanged).
 template <typename T, int SIGN>
 __device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alpha, T eps, T (&F)[8]) {
-    const T c1312 = (T)(13.0 / 12.0), sixth = (T)(1.0 / 6.0);
+    const T c133 = (T)(13.0 / 3.0), sixth = (T)(1.0 / 6.0), eps4 = (T)4 * eps;
     // split flux at the points 8g - 2 .. 8g + 10 (index j = point - 8g + 2)
     T f[13];
     #pragma unroll
@@ -106,7 +136,7 @@ __device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alph
     #pragma unroll
     for (int j = 1; j < 12; ++j) {
         D2[j] = dd[j] - dd[j - 1];
-        A[j] = fma(c1312 * D2[j], D2[j], eps);
+        A[j] = fma(c133 * D2[j], D2[j], eps4);
     }
     #pragma unroll
     for (int j = 1; j < 11; ++j) G[j] = D2[j] - D2[j + 1];
@@ -118,9 +148,9 @@ __device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alph
         // d between c and a / c and b, oriented along the stencil
         const T dca = SIGN > 0 ? dd[a] : -dd[c];     // f_c - f_a
         const T dbc = SIGN > 0 ? dd[c] : -dd[b];     // f_b - f_c
-        const T b0 = fma((T)0.5, D2[a], dca);
-        const T b1 = (T)0.5 * (dca + dbc);
-        const T b2 = fma((T)0.5, D2[b], -dbc);
+        const T b0 = fma((T)2, dca, D2[a]);
+        const T b1 = dca + dbc;
+        const T b2 = fma((T)-2, dbc, D2[b]);
         T s0 = fma(b0, b0, A[a]), s1 = fma(b1, b1, A[c]), s2 = fma(b2, b2, A[b]);
         s0 *= s0; s1 *= s1; s2 *= s2;
         const T t12 = s1 * s2, t02 = s0 * s2, t01 = s0 * s1;
@@ -138,18 +168,19 @@ __device__ __forceinline__ void weno_group(const T (&u)[16], T nlq, T ha, T alph
 // ------------------------------------------------------------------ block helpers
 
 // Max over the tpr threads of one line (lines are aligned groups of tpr
-// consecutive threads; tpr is a power of two).  red: one LDS slot per wave.
+// consecutive threads; tpr is a power of two), NaN if any value is NaN.
+// red: one LDS slot per wave.
 template <typename T>
 __device__ __forceinline__ T line_max(T v, int tpr, T* red) {
     const int w = tpr < 64 ? tpr : 64;
-    for (int o = w >> 1; o > 0; o >>= 1) v = tmax(v, __shfl_xor(v, o));
+    for (int o = w >> 1; o > 0; o >>= 1) v = nmax(v, __shfl_xor(v, o));
     if (tpr > 64) {
         const int wave = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) red[wave] = v;
         __syncthreads();
         const int nw = tpr >> 6, first = (threadIdx.x / tpr) * nw;
         T m = red[first];
-        for (int i = 1; i < nw; ++i) m = tmax(m, red[first + i]);
+        for (int i = 1; i < nw; ++i) m = nmax(m, red[first + i]);
         v = m;
         __syncthreads();
     }
@@ -209,49 +240,43 @@ __device__ __forceinline__ SpecIdx spec_idx(int log2W, int n_y, bool tiled) {
 }
 
 // Positions of the pair (k, M - k), k = min(t + q*tpr, M/2), in a spectral
-// row: X index of k, of (M - k) mod M, and twiddle index k << sh.  PROG: the
-// row is tiled and tpr (= M/16) is a multiple of the tile width, so k moves
-// by whole tiles from one q to the next and the positions are arithmetic
-// progressions in q (q < 8; q = 8 is k = M/2, used by t = 0 only).
-template <bool PROG>
+// row: X index of k, of (M - k) mod M, and twiddle index k << sh.
 struct PairIdx {
-    unsigned k0, m0, w0, step, wstep, kh, wh;
     int t, tpr, M, sh;
     SpecIdx ix;
-    __device__ __forceinline__ PairIdx(SpecIdx ix_, int M_, int t_, int tpr_, int sh_)
-        : t(t_), tpr(tpr_), M(M_), sh(sh_), ix(ix_) {
-        if constexpr (PROG) {
-            step = __umul24((unsigned)tpr >> ix.lw, ix.stride);
-            k0 = ix(t);
-            m0 = ix(M - t);                       // ix(M) (t = 0) is only a base for q >= 1
-            w0 = (unsigned)t << sh;
-            wstep = (unsigned)tpr << sh;
-            kh = ix(M >> 1);
-            wh = (unsigned)(M >> 1) << sh;
-        }
-    }
-    __device__ __forceinline__ unsigned xk(int q) const {
-        if constexpr (PROG) return q < 8 ? k0 + q * step : kh;
-        else return ix(min(t + q * tpr, M >> 1));
-    }
-    __device__ __forceinline__ unsigned xm(int q) const {
-        if constexpr (PROG) return q == 0 ? (t == 0 ? k0 : m0) : q < 8 ? m0 - q * step : kh;
-        else return ix((M - min(t + q * tpr, M >> 1)) & (M - 1));
-    }
-    __device__ __forceinline__ unsigned w(int q) const {
-        if constexpr (PROG) return q < 8 ? w0 + q * wstep : wh;
-        else return (unsigned)min(t + q * tpr, M >> 1) << sh;
-    }
+    __device__ __forceinline__ unsigned xk(int q) const { return ix(min(t + q * tpr, M >> 1)); }
+    __device__ __forceinline__ unsigned xm(int q) const { return ix((M - min(t + q * tpr, M >> 1)) & (M - 1)); }
+    __device__ __forceinline__ unsigned w(int q) const { return (unsigned)min(t + q * tpr, M >> 1) << sh; }
 };
 
-template <typename T, bool PROG = false>
+// One pair of the inverse: from X_k, X_{M-k} and the twiddle e^{-2 pi i k/N},
+// Z_k and Z_{M-k} (both scaled by inv_n).
+template <typename T>
+__device__ __forceinline__ void c2r_pair(cpx<T> xk, cpx<T> xm, cpx<T> w, T inv_n, cpx<T>& zk, cpx<T>& zm) {
+    const cpx<T> A = {xk.x + xm.x, xk.y - xm.y};
+    const cpx<T> D = {xk.x - xm.x, xk.y + xm.y};
+    const cpx<T> P = mul_si<1>(cmul(conj(w), D));    // i e^{+2 pi i k/N} D
+    zk = inv_n * (A + P);
+    zm = inv_n * conj(A - P);
+}
+// One pair of the forward: X_k and X_{M-k} from Z_k, Z_{M-k}.
+template <typename T>
+__device__ __forceinline__ void r2c_pair(cpx<T> zk, cpx<T> zm, cpx<T> w, cpx<T>& xk, cpx<T>& xm) {
+    const cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+    const cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
+    const cpx<T> Q = mul_si<1>(cmul(w, D));          // i e^{-2 pi i k/N} D
+    xk = A - Q;
+    xm = conj(A + Q);
+}
+
+template <typename T>
 __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int M, int t,
                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw, T inv_n) {
     // pairs k = t + q*tpr <= M/2, q < 9 (tpr = M/16); all loads of the thread are
     // issued before any is used, so their latencies overlap
     const int sh = log2_ntw - ilog2(2 * M);
     constexpr int Q = 9;
-    const PairIdx<PROG> pi(ix, M, t, tpr, sh);
+    const PairIdx pi{t, tpr, M, sh, ix};
     cpx<T> xk[Q], xm[Q], wv[Q];
     #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -268,41 +293,125 @@ __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix
             lds[padi(base)] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
             continue;
         }
-        const cpx<T> A = {xk[q].x + xm[q].x, xk[q].y - xm[q].y};
-        const cpx<T> D = {xk[q].x - xm[q].x, xk[q].y + xm[q].y};
-        const cpx<T> P = mul_si<1>(cmul(conj(wv[q]), D));    // i e^{+2 pi i k/N} D
-        lds[padi(base + k)] = inv_n * (A + P);
-        if (2 * k != M) lds[padi(base + M - k)] = inv_n * conj(A - P);
+        cpx<T> zk, zm;
+        c2r_pair(xk[q], xm[q], wv[q], inv_n, zk, zm);
+        lds[padi(base + k)] = zk;
+        if (2 * k != M) lds[padi(base + M - k)] = zm;
     }
 }
 
-template <typename T, bool PROG = false>
+template <typename T>
 __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int M, int t,
                                          int tpr, const cpx<T>* __restrict__ tw, int log2_ntw) {
     const int sh = log2_ntw - ilog2(2 * M);
-    const PairIdx<PROG> pi(ix, M, t, tpr, sh);
+    const PairIdx pi{t, tpr, M, sh, ix};
     #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int k = t + q * tpr;
         if (k > (M >> 1)) continue;
         const cpx<T> zk = lds[padi(base + k)];
         const cpx<T> zm = lds[padi(base + ((M - k) & (M - 1)))];
-        const cpx<T> A = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
-        const cpx<T> D = {(T)0.5 * (zk.x - zm.x), (T)0.5 * (zk.y + zm.y)};
-        const cpx<T> Q = mul_si<1>(cmul(tw[pi.w(q)], D));    // i e^{-2 pi i k/N} D
+        cpx<T> a, b;
+        r2c_pair(zk, zm, tw[pi.w(q)], a, b);
         if (k == 0) {
-            X[0] = cpx<T>{A.x - Q.x, A.x + Q.x};
+            X[0] = cpx<T>{a.x, b.x};   // slot 0 = (X_0, X_M) = (A - Q, A + Q) real parts
             continue;
         }
-        X[pi.xk(q)] = A - Q;
-        if (2 * k != M) X[pi.xm(q)] = conj(A + Q);
+        X[pi.xk(q)] = a;
+        if (2 * k != M) X[pi.xm(q)] = b;
+    }
+}
+
+// The same two for tiled spectra with W <= tpr = M/16 and tpr a multiple of
+// 16 (M >= 256).  For q < 8 the pair k = t + q tpr lies in [0, M/2); from one
+// q to the next its tile position, that of M - k and its twiddle index move
+// by wave-uniform steps (whole tiles), and so do the padded LDS slots of k
+// and M - k (16-aligned strides).  The global accesses are buffer accesses
+// with a per-thread base and a uniform offset, the LDS ones a per-thread
+// base plus a uniform offset; k = 0 (t = 0, q = 0) is a select and
+// k = M/2 (t = 0 only) is done apart.  X: the instance's array (a
+// block-uniform address, so the buffer descriptor stays in scalar
+// registers), ro: the row's element offset in it.
+template <typename T>
+__device__ __forceinline__ void c2r_pre_prog(const cpx<T>* X, unsigned ro, SpecIdx ix, cpx<T>* lds, int base, int M,
+                                             int t, int tpr, const cpx<T>* tw, int log2_ntw, T inv_n) {
+    constexpr unsigned E = sizeof(cpx<T>);
+    const int sh = log2_ntw - ilog2(2 * M);
+    const unsigned step = __umul24((unsigned)tpr >> ix.lw, ix.stride) * E;   // bytes per q
+    const unsigned wstep = ((unsigned)tpr << sh) * E;
+    const unsigned k0 = (ro + ix(t)) * E;                // k at q = 0
+    const unsigned m7 = (ro + ix(M - t - 7 * tpr)) * E;  // M - k at q = 7
+    const unsigned w0 = ((unsigned)t << sh) * E;
+    const auto xr = buf_rsrc(X), wr = buf_rsrc(tw);
+    cpx<T> xk[8], xm[8], wv[8];
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        xk[q] = buf_ld<T>(xr, k0, q * step);
+        // at q = 0, M - k = M for t = 0 lies outside the row: read X_0 there
+        xm[q] = q == 0 ? buf_ld<T>(xr, t == 0 ? k0 : m7 + 7 * step, 0) : buf_ld<T>(xr, m7, (7 - q) * step);
+        wv[q] = buf_ld<T>(wr, w0, q * wstep);
+    }
+    const int t17 = tpr + (tpr >> 4);
+    const int pk = padi(base + t), pm = padi(base + M - t);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        cpx<T> zk, zm;
+        c2r_pair(xk[q], xm[q], wv[q], inv_n, zk, zm);
+        if (q == 0 && t == 0) zk = cpx<T>{(xk[0].x + xk[0].y) * inv_n, (xk[0].x - xk[0].y) * inv_n};
+        lds[pk + q * t17] = zk;
+        if (q > 0 || t != 0) lds[pm - q * t17] = zm;
+    }
+    if (t == 0) {
+        // k = M/2 pairs with itself
+        const cpx<T> x = X[ro + ix(M >> 1)];
+        cpx<T> zk, zm;
+        c2r_pair(x, x, tw[(unsigned)(M >> 1) << sh], inv_n, zk, zm);
+        lds[padi(base + (M >> 1))] = zk;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void r2c_post_prog(const cpx<T>* lds, int base, cpx<T>* X, unsigned ro, SpecIdx ix, int M,
+                                              int t, int tpr, const cpx<T>* tw, int log2_ntw) {
+    constexpr unsigned E = sizeof(cpx<T>);
+    const int sh = log2_ntw - ilog2(2 * M);
+    const unsigned step = __umul24((unsigned)tpr >> ix.lw, ix.stride) * E;
+    const unsigned wstep = ((unsigned)tpr << sh) * E;
+    const unsigned k0 = (ro + ix(t)) * E;
+    const unsigned m7 = (ro + ix(M - t - 7 * tpr)) * E;
+    const unsigned w0 = ((unsigned)t << sh) * E;
+    const auto xr = buf_rsrc(X), wr = buf_rsrc(tw);
+    cpx<T> wv[8];
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) wv[q] = buf_ld<T>(wr, w0, q * wstep);
+    const int t17 = tpr + (tpr >> 4);
+    const int pk = padi(base + t), pm = padi(base + M - t);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const cpx<T> zk = lds[pk + q * t17];
+        const cpx<T> zm = lds[q == 0 ? (t == 0 ? pk : pm) : pm - q * t17];   // (M - k) mod M
+        cpx<T> a, b;
+        r2c_pair(zk, zm, wv[q], a, b);
+        if (q == 0 && t == 0) a = cpx<T>{a.x, b.x};   // slot 0 = (X_0, X_M)
+        buf_st<T>(xr, k0, q * step, a);
+        // at q = 0, M - k = M for t = 0 lies outside the row: that thread
+        // stores slot 0 a second time instead (same address, same value)
+        if (q == 0) buf_st<T>(xr, t == 0 ? k0 : m7 + 7 * step, 0, t == 0 ? a : b);
+        else buf_st<T>(xr, m7, (7 - q) * step, b);
+    }
+    if (t == 0) {
+        const cpx<T> z = lds[padi(base + (M >> 1))];
+        cpx<T> a, b;
+        r2c_pair(z, z, tw[(unsigned)(M >> 1) << sh], a, b);
+        X[ro + ix(M >> 1)] = a;
     }
 }
 
 // MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B (b via WENO5).
 // MODE 3: as MODE 2, and also stores the physical line u (for the adjoint).
-// PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width in
-// every instance (progression indexing of the pre/post-processing pairs).
+// PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width and
+// of 16 in every instance (progression indexing of the pre/post-processing
+// pairs).
 template <typename T, int MODE, bool PROG = false>
 __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __restrict__ descs,
                                                           const TauItem* __restrict__ items,
@@ -345,12 +454,16 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
         lds_fft<T, -1>(lds, base, M, t, active, twst);
-        if (active) r2c_post<T, PROG>(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+        if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
         return;
     }
 
     // inverse tau-transform of C~ into the line buffer
-    if (active) c2r_pre<T, PROG>(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    if (active) {
+        if constexpr (PROG) c2r_pre_prog(Cin + d.off_state, (unsigned)row << d.log2W, ix, lds, base, M, t, tpr, tw,
+                                         log2_ntw, (T)1 / (T)N);
+        else c2r_pre(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    }
     __syncthreads();
     lds_fft<T, 1>(lds, base, M, t, active, twst);
 
@@ -363,22 +476,19 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         if (MODE == 1) return;
     }
 
-    // ---- LF speed alpha = |nl(x_node)| max|u| over the line (exact in any precision)
+    // ---- LF speed alpha = |nl(x_node)| max|u| over the line (exact in any precision);
+    // the maximum propagates NaN and Inf, so it also flags a non-finite line
     T mx = 0;
-    int bad = 0;
     if (active) {
         #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const quad<T> v = lds_quad(lds, base, t + q * tpr);
             #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                bad |= !finite_val(v.v[i]);
-                mx = tmax(mx, (T)fabs(v.v[i]));
-            }
+            for (int i = 0; i < 4; ++i) mx = nmax(mx, (T)fabs(v.v[i]));
         }
     }
     mx = line_max(mx, tpr, redT);
-    bad = line_or(bad, tpr, redI);
+    const bool bad = !finite_val(mx);
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
     const T nlT = (T)nl;
     const T alpha = (T)fabs(nl) * mx;
@@ -445,7 +555,11 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
     }
     __syncthreads();
     lds_fft<T, -1>(lds, base, M, t, active, twst);
-    if (active) r2c_post<T, PROG>(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+    if (active) {
+        if constexpr (PROG) r2c_post_prog(lds, base, Bout + d.off_state, (unsigned)row << d.log2W, ix, M, t, tpr, tw,
+                                          log2_ntw);
+        else r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+    }
 }
 
 // ------------------------------------------------------------------ multiplier tables
@@ -993,7 +1107,6 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     const bool active = (r < (TAU_THREADS * 16) / M) && (row < d.n_y);
     const int gb = r * M;                          // cotangent line
     const int ub = TAU_THREADS * 16 + r * M;        // u line (second half of the buffer)
-    const int Nc = M >> 1;
     const SpecIdx ix = spec_idx(d.log2W, d.n_y, true);
     const long long so = d.off_state + ((long long)row << d.log2W);
 
