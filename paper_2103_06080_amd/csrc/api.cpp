@@ -41,6 +41,7 @@ struct kzk_plan {
     int y_threads = 0;
     int y_grid = 0;                       // persistent y-pass blocks (resident at once)
     int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
+    int y_full = 0;                       // every instance has W n_y = 16 y_threads and n_y >= 512 (full y tiles)
     bool any_D_sched = false;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
@@ -175,7 +176,10 @@ kzk_status layout(kzk_plan* p) {
     p->tau_prog = 1;
     for (const InstDesc& d : p->desc)
         if (d.M / 16 < d.W || d.M < 256) p->tau_prog = 0;
-    p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->device);
+    p->y_full = 1;
+    for (const InstDesc& d : p->desc)
+        if (d.W * d.n_y != 16 * p->y_threads || d.n_y < 512) p->y_full = 0;
+    p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->y_full, p->device);
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dTau, tau.data(), sizeof(TauItem) * tau.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -219,10 +223,10 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
 hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
-        return kzk::launch_y<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB,
-                                    p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
-    return kzk::launch_y<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC, p->dB, p->dP,
-                                 p->dU, p->dTab, p->dTwSt, step, p->stream);
+        return kzk::launch_y<float>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
+                                    p->dB, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+    return kzk::launch_y<double>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
+                                 p->dB, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).

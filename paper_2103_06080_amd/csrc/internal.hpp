@@ -48,13 +48,15 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
 // y-pass over n_items column tiles with at most max_blocks persistent blocks
 // (0: one block per tile).  step: index into the D schedule of instances
 // whose multipliers the y-pass computes itself (those with D_step; stage 1
-// then writes their h Phi2 table for stage 2).
+// then writes their h Phi2 table for stage 2).  full: every instance has
+// W n_y = 16 nt and n_y >= 512 (full tiles; progression addressing).
 template <typename T>
-hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                    void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
+hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                    int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
                     hipStream_t s);
-// blocks of the y-pass kernels (block size nt) resident at once on the device
-int y_resident_blocks(int dtype_is_f64, int nt, int device);
+// blocks of the y-pass kernels (block size nt, full-tile variant or not)
+// resident at once on the device
+int y_resident_blocks(int dtype_is_f64, int nt, int full, int device);
 
 template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,

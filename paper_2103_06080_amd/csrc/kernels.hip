@@ -714,12 +714,23 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // every array; its DC is invariant and its Nyquist multipliers are scalars.
 // FP32 blocks of up to 512 threads are held to 128 VGPRs so that several
 // share a compute unit (as many as their LDS allows).
-template <typename T, int NT, int STAGE>
+//
+// FULL (every instance has W n_y = 16 NT and n_y >= 512): element
+// e = tid + q NT of a tile is row j0 + q dq of column c (c = tid mod W,
+// j0 = tid / W, dq = n_y/16, a multiple of 32), so its global offset moves by
+// the uniform q NT (buffer accesses with a per-thread base) and its padded
+// LDS slot by the uniform q (dq + dq/16); no slot is out of range, and the
+// first column of the first tile is one per-thread predicate.  Columns start
+// at LDS slot c (P + 32) + (c R mod 32) (P = padded n_y, R = 64/W rows of a
+// column per wave), so that the W row runs of one wave access cover the LDS
+// banks evenly instead of starting on the same bank.
+template <typename T, int NT, int STAGE, bool FULL>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
         const cpx<T>* __restrict__ B, cpx<T>* __restrict__ P, cpx<T>* __restrict__ U, cpx<T>* __restrict__ tabs,
         const cpx<T>* __restrict__ twst, int step) {
-    __shared__ alignas(32) cpx<T> lds[padded(NT * 16)];
+    __shared__ alignas(32) cpx<T> lds[padded(NT * 16) + (FULL ? NT : 0)];
+    constexpr unsigned E = sizeof(cpx<T>);
     const int tid = threadIdx.x;
     // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...
     const cpx<T>* src = STAGE == 0 ? C : B;
@@ -753,32 +764,165 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // instead of reading tables rebuilt every step, and stores h Phi2 / n_y
     // into its table for stage 2
     const bool otf = STAGE == 1 && d.D_step != nullptr;
+    // FULL geometry (unused otherwise)
+    const int c = tid & (W - 1), j0 = tid >> lw;
+    const int dq = Ny >> 4, sq = dq + (dq >> 4);
+    const int Pn = Ny + (Ny >> 4);
+    auto colbase = [&](int col) { return col * (Pn + 32) + ((col << (6 - lw)) & 31); };
+    const int s0 = colbase(c) + padi(j0);               // slot of row j0 (q = 0)
+    const int s1 = colbase(c) + padi(Ny - j0);          // slot of row Ny - j0 (q = 0)
+    const bool keep_c = !(col0 && c == 0);
+    cpx<T>* fbuf = FULL ? lds + colbase(fc) : lds;      // this thread's FFT column
+    const int fbase = FULL ? 0 : fc * Ny;
 
-    tile_fetch<T, NT>(src + to, ne, tid, vr, vi);
+    if constexpr (FULL) {
+        const auto rs = buf_rsrc(src + to);
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpx<T> x = buf_ld<T>(rs, tid * E, q * NT * E);
+            vr[q] = x.x;
+            vi[q] = x.y;
+        }
+    } else {
+        tile_fetch<T, NT>(src + to, ne, tid, vr, vi);
+    }
     if (Ny != tw_ny) {
         lds_fft_twiddles<T>(Ny, ft, twst, ytw);
         tw_ny = Ny;
     }
-    tile_put<T, NT>(lds, vr, vi, ne, tid, W, lw, Ny);
+    if constexpr (FULL) {
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) lds[s0 + q * sq] = cpx<T>{vr[q], vi[q]};
+    } else {
+        tile_put<T, NT>(lds, vr, vi, ne, tid, W, lw, Ny);
+    }
     __syncthreads();
     if (STAGE == 0) {
-        lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
-        #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = tid + q * NT;
-            if (e < ne) Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
+        lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
+        if constexpr (FULL) {
+            const auto rc = buf_rsrc(Ct), ru = buf_rsrc(Ut);
+            #pragma unroll
+            for (int q = 0; q < 16; ++q)
+                buf_st<T>(ru, tid * E, q * NT * E, keep_c ? lds[s0 + q * sq] : buf_ld<T>(rc, tid * E, q * NT * E));
+        } else {
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = tid + q * NT;
+                if (e < ne) Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
+            }
         }
         __syncthreads();
         continue;
     }
 
-    lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
+    lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
     // indices n and Ny - n.  A thread has at most 9 half-tile items
     // (Nh * W <= 8 NT + W); their global loads are issued before use.
     const int nh = Nh * W;
     constexpr int QH = 9;
-    if (STAGE == 1 && otf) {
+    if constexpr (FULL) {
+        // item q: h = tid + q NT, row n = j0 + q dq; q < 8 for every thread,
+        // q = 8 (n = Ny/2) for tid < W only.  The partner row Ny - n exists
+        // for q = 1..7 and for q = 0 with j0 > 0; its element is
+        // ne - tid + 2c - q NT.
+        const auto rU = buf_rsrc(Ut), rP = buf_rsrc(Pt), rE = buf_rsrc(tE), rP1 = buf_rsrc(tP1), rP2 = buf_rsrc(tP2);
+        const bool first = tid < W;                    // rows 0 and Ny/2 of column c
+        const unsigned v0 = tid * E;                   // element h at q = 0
+        const unsigned v8 = min(tid, W - 1) * E;       // h at q = 8, clamped to the tile's table rows
+        const unsigned vm = (unsigned)(ne - tid + 2 * c - 8 * NT) * E;   // partner at q = 8 (base)
+        const unsigned vm0 = first ? v0 : (unsigned)(ne - tid + 2 * c) * E;  // partner at q = 0
+        auto vpart = [&](int q) { return q == 0 ? vm0 : vm; };
+        auto spart = [&](int q) { return q == 0 ? 0u : (unsigned)(8 - q) * NT * E; };
+        auto vself = [&](int q) { return q == 8 ? v8 : v0; };
+        if (STAGE == 1 && otf) {
+            // one item at a time (the FP64 multiplier code needs the registers);
+            // the U loads of the next item are in flight during this item's
+            // multipliers.  Column 0 of the first tile is handled pointwise below.
+            cpx<T> u0 = buf_ld<T>(rU, v0, 0), u1 = buf_ld<T>(rU, vm0, 0);
+            #pragma unroll
+            for (int q = 0; q < QH; ++q) {
+                cpx<T> x0 = u0, x1 = u1;
+                if (q + 1 < QH) {
+                    x0 = buf_ld<T>(rU, vself(q + 1), (q + 1) * NT * E);
+                    if (q + 1 < 8) x1 = buf_ld<T>(rU, vpart(q + 1), spart(q + 1));
+                }
+                if (q < 8 || first) {
+                    const int n = j0 + q * dq;
+                    const bool two = q > 0 ? q < 8 : !first;
+                    cpx<T> E0 = {(T)0, (T)0}, P1 = E0, P2 = E0;
+                    if (m0 + c > 0) {
+                        mode_multipliers<T>(d, m0 + c, n, step, E0, P1, P2);
+                    } else if (n == 0) {
+                        T e, p1, p2;
+                        nyquist_multipliers<T>(d, e, p1, p2);
+                        P2 = cpx<T>{p2, (T)0};
+                    }
+                    buf_st<T>(rP2, vself(q), q * NT * E, P2);
+                    {
+                        const int li = s0 + q * sq;
+                        const cpx<T> bh = lds[li];
+                        const cpx<T> EU = cmul(E0, u0);
+                        if (keep_c) buf_st<T>(rP, vself(q), q * NT * E, EU + cmul(P1 - P2, bh));
+                        lds[li] = EU + cmul(P1, bh);
+                    }
+                    if (two) {
+                        const int li = s1 - q * sq;
+                        const cpx<T> bh = lds[li];
+                        const cpx<T> EU = cmul(E0, u1);
+                        if (keep_c) buf_st<T>(rP, vpart(q), spart(q), EU + cmul(P1 - P2, bh));
+                        lds[li] = EU + cmul(P1, bh);
+                    }
+                }
+                u0 = x0;
+                u1 = x1;
+            }
+        } else {
+            #pragma unroll
+            for (int q0 = 0; q0 < QH; q0 += 3) {
+                cpx<T> tb[3][3], ua[3][2];
+                #pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int qq = q0 + q;
+                    const unsigned vs = vself(qq), ss = qq * NT * E;
+                    if (STAGE == 1) {
+                        tb[q][0] = buf_ld<T>(rE, vs, ss);
+                        tb[q][1] = buf_ld<T>(rP1, vs, ss);
+                        tb[q][2] = buf_ld<T>(rP2, vs, ss);
+                        ua[q][0] = buf_ld<T>(rU, vs, ss);
+                        ua[q][1] = qq < 8 ? buf_ld<T>(rU, vpart(qq), spart(qq)) : ua[q][0];
+                    } else {
+                        tb[q][2] = buf_ld<T>(rP2, vs, ss);
+                        ua[q][0] = buf_ld<T>(rP, vs, ss);
+                        ua[q][1] = qq < 8 ? buf_ld<T>(rP, vpart(qq), spart(qq)) : ua[q][0];
+                    }
+                }
+                #pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int qq = q0 + q;
+                    if (!(qq < 8 || first)) continue;
+                    const bool two = qq > 0 ? qq < 8 : !first;
+                    #pragma unroll
+                    for (int pass = 0; pass < 2; ++pass) {
+                        if (pass == 1 && !two) break;
+                        const int li = pass ? s1 - qq * sq : s0 + qq * sq;
+                        const unsigned vv = pass ? vpart(qq) : vself(qq);
+                        const unsigned ss = pass ? spart(qq) : (unsigned)qq * NT * E;
+                        const cpx<T> bh = lds[li];
+                        if (STAGE == 1) {
+                            const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
+                            if (keep_c) buf_st<T>(rP, vv, ss, EU + cmul(tb[q][1] - tb[q][2], bh));
+                            lds[li] = EU + cmul(tb[q][1], bh);
+                        } else {
+                            const cpx<T> un = ua[q][pass] + cmul(tb[q][2], bh);
+                            if (keep_c) buf_st<T>(rU, vv, ss, (T)Ny * un);
+                            lds[li] = un;
+                        }
+                    }
+                }
+            }
+        }
+    } else if (STAGE == 1 && otf) {
         // one item at a time (the FP64 multiplier code needs the registers);
         // the U loads of the next item are in flight during this item's
         // multipliers.  Column 0 of the first tile is handled pointwise below
@@ -881,8 +1025,16 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     }
     }
     __syncthreads();
-    lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
-    tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
+    lds_fft_held<T, 1>(fbuf, fbase, Ny, ft, act, ytw);
+    if constexpr (FULL) {
+        const auto rc = buf_rsrc(Ct);
+        if (keep_c) {
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) buf_st<T>(rc, tid * E, q * NT * E, lds[s0 + q * sq]);
+        }
+    } else {
+        tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
+    }
 #undef KZK_LI
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
@@ -1321,7 +1473,7 @@ hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, 
     return hipGetLastError();
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool FULL>
 static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
                               void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
                               hipStream_t s) {
@@ -1333,34 +1485,36 @@ static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
     return hipGetLastError();
 }
 
 template <typename T, int NT>
-static int y_resident_nt(int device) {
+static int y_resident_nt(int device, bool full) {
     int ncu = 0, per = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
         return 0;
     int lo = 1 << 30;
-    const void* fns[3] = {(const void*)y_kernel<T, NT, 0>, (const void*)y_kernel<T, NT, 1>,
-                          (const void*)y_kernel<T, NT, 2>};
-    for (const void* f : fns) {
+    const void* fns[2][3] = {{(const void*)y_kernel<T, NT, 0, false>, (const void*)y_kernel<T, NT, 1, false>,
+                              (const void*)y_kernel<T, NT, 2, false>},
+                             {(const void*)y_kernel<T, NT, 0, true>, (const void*)y_kernel<T, NT, 1, true>,
+                              (const void*)y_kernel<T, NT, 2, true>}};
+    for (const void* f : fns[full ? 1 : 0]) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, NT, 0) != hipSuccess || per <= 0) return 0;
         lo = per < lo ? per : lo;
     }
     return ncu * lo;
 }
 
-int y_resident_blocks(int is_f64, int nt, int device) {
+int y_resident_blocks(int is_f64, int nt, int full, int device) {
     switch (nt) {
-    case 256: return is_f64 ? y_resident_nt<double, 256>(device) : y_resident_nt<float, 256>(device);
-    case 512: return is_f64 ? y_resident_nt<double, 512>(device) : y_resident_nt<float, 512>(device);
-    case 1024: return is_f64 ? 0 : y_resident_nt<float, 1024>(device);
+    case 256: return is_f64 ? y_resident_nt<double, 256>(device, full) : y_resident_nt<float, 256>(device, full);
+    case 512: return is_f64 ? y_resident_nt<double, 512>(device, full) : y_resident_nt<float, 512>(device, full);
+    case 1024: return is_f64 ? 0 : y_resident_nt<float, 1024>(device, full);
     default: return 0;
     }
 }
@@ -1370,21 +1524,33 @@ bool y_threads_supported(int is_f64, int nt) {
     return nt == 1024 && !is_f64;
 }
 
-template <typename T>
-hipError_t launch_y(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                    void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
-                    hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
+template <typename T, bool FULL>
+static hipError_t launch_y_full(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                                int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst,
+                                int step, hipStream_t s) {
     switch (nt) {
-    case 256: return launch_y_nt<T, 256>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
-    case 512: return launch_y_nt<T, 512>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
+    case 256:
+        return launch_y_nt<T, 256, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
+    case 512:
+        return launch_y_nt<T, 512, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step,
-                                        s);
+            return launch_y_nt<T, 1024, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+                                              step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                    int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
+                    hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    return full ? launch_y_full<T, true>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+                                         step, s)
+                : launch_y_full<T, false>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+                                          step, s);
 }
 
 template <typename T>
@@ -1470,8 +1636,8 @@ void stage_twiddles(double* out) {
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
                                       const void*, const void*, int, int, int, int, unsigned*, hipStream_t);         \
-    template hipError_t launch_y<T>(int, int, const InstDesc*, const YItem*, int, int, void*, const void*, void*,   \
-                                    void*, void*, const void*, int, hipStream_t);                                    \
+    template hipError_t launch_y<T>(int, int, int, const InstDesc*, const YItem*, int, int, void*, const void*,     \
+                                    void*, void*, void*, const void*, int, hipStream_t);                             \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
