@@ -71,13 +71,31 @@ def test_weno_b_matches_oracle(torch_cuda, orc, dtype, nt, ny):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("nt,ny,n_steps,A", [(64, 16, 1, 0.0), (256, 128, 10, 1e-3), (128, 256, 5, 0.0),
-                                             (512, 64, 7, 2e-4), (32, 4096, 2, 0.0), (8192, 32, 2, 1e-4)])
+                                             (512, 64, 7, 2e-4), (32, 4096, 2, 0.0), (8192, 32, 2, 1e-4),
+                                             (512, 1024, 3, 1e-4), (2048, 1024, 2, 1e-4)])
 def test_step_matches_oracle(torch_cuda, orc, dtype, nt, ny, n_steps, A):
     from paper_2103_06080_amd import kzk
     p = small(nt, ny, n_steps=n_steps, A=A)
     plan = kzk.Plan(p, dtype=dtype)
     u = plan.pack([p.u0])
     plan.step(u, 0, n_steps)
+    assert plan.poll() == 0
+    got = plan.unpack(u)[0]
+    ref = orc.run(p)
+    assert rel_l2(got, ref) < TOL[dtype], (rel_l2(got, ref))
+
+
+@pytest.mark.parametrize("dtype,yt", [("f64", 256), ("f64", 512), ("f32", 256), ("f32", 512), ("f32", 1024)])
+def test_full_tile_y_pass_matches_oracle(torch_cuda, orc, dtype, yt):
+    """Grids whose y-tiles fill every thread slot (W n_y = 16 threads, n_y >= 512)
+    take the full-tile y-pass; tau-lines of M >= 256 the progression-indexed
+    pre/post-processing.  Scheduled D: stage 1 evaluates the multipliers."""
+    from paper_2103_06080_amd import kzk
+    p = small(1024, 1024, n_steps=3, A=1e-4)
+    plan = kzk.Plan(p, dtype=dtype, y_threads=yt)
+    assert plan.y_threads == yt
+    u = plan.pack([p.u0])
+    plan.step(u, 0, p.n_steps)
     assert plan.poll() == 0
     got = plan.unpack(u)[0]
     ref = orc.run(p)
