@@ -46,6 +46,7 @@ struct kzk_plan {
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
     void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dU = nullptr, *dTab = nullptr, *dTw = nullptr;
+    void* dSig = nullptr;                 // flux-difference symbols, sum of M over the solves
     InstDesc* dDesc = nullptr;
     TauItem* dTau = nullptr;    // tau-pass work list (TAU_THREADS * 16 / M lines per item)
     YItem* dY = nullptr;
@@ -417,6 +418,37 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
             p->desc[i].nl_node = p->nlsched[i].empty() ? nullptr : p->dSched + offN[i];
         }
     }
+    // flux-difference symbols sigma_m = -(2 sin^2(pi m/n_tau) + i sin(2 pi m/n_tau)) / dtau
+    // (FP64, half-angle form for the low modes; m = 0 zero), in the working precision
+    {
+        size_t tot = 0;
+        for (int i = 0; i < n_inst; ++i) tot += (size_t)p->desc[i].M;
+        std::vector<double> sg(2 * tot);
+        size_t o = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            const InstDesc& d = p->desc[i];
+            for (int m = 0; m < d.M; ++m, ++o) {
+                const double a = M_PI * (double)m / (double)d.n_tau;
+                const double sh = std::sin(a), ch = std::cos(a);
+                sg[2 * o] = m ? -2.0 * sh * sh / d.dtau : 0.0;
+                sg[2 * o + 1] = m ? -2.0 * sh * ch / d.dtau : 0.0;
+            }
+        }
+        hipError_t e = hipSuccess;
+        if ((st = dev_alloc(p, &p->dSig, sg.size() * p->esz)) != KZK_OK) { kzk_destroy(p); return st; }
+        if (p->dtype == KZK_F32) {
+            std::vector<float> f(sg.begin(), sg.end());
+            e = hipMemcpy(p->dSig, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(p->dSig, sg.data(), sg.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+        o = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            p->desc[i].sigma = (const char*)p->dSig + o * 2 * p->esz;
+            o += (size_t)p->desc[i].M;
+        }
+    }
     // twiddles exp(-2 pi i k / ntw) in FP64, stored in the working precision
     {
         std::vector<double> tw(2 * (size_t)ntw);
@@ -560,6 +592,13 @@ kzk_status kzk_eval_b(kzk_plan* p, const void* u, int32_t node, void* b) {
     if (node < 0 || (p->steps_limit >= 0 && node > p->steps_limit)) return KZK_ERR_STATE;
     if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
     if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, node) != hipSuccess) return KZK_ERR_DEVICE;
+    // the tau-pass leaves the spectrum of the face fluxes: apply the difference
+    for (int i = 0; i < p->n_inst; ++i) {
+        const long long n = (long long)p->desc[i].M * p->desc[i].n_y;
+        if ((p->dtype == KZK_F32 ? kzk::launch_flux_diff<float>(p->dDesc, i, n, p->dB, p->stream)
+                                 : kzk::launch_flux_diff<double>(p->dDesc, i, n, p->dB, p->stream)) != hipSuccess)
+            return KZK_ERR_DEVICE;
+    }
     if (tau(p, 1, nullptr, b, p->dB, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
     return KZK_OK;
 }

@@ -30,6 +30,9 @@ struct InstDesc {
     double D_const, nl_const, cfl_max;
     const double* nl_node;   // device [n_steps_max+1] or nullptr -> nl_const
     const double* D_step;    // device [n_steps_max]   or nullptr -> D_const
+    // device [M] complex (working precision): flux-difference symbol sigma_m
+    // = -(1 - e^{-2 pi i m / n_tau}) / dtau of tau-mode m (m = 0: zero)
+    const void* sigma;
 };
 
 struct TauItem { int inst, row0; };
@@ -61,6 +64,11 @@ int y_resident_blocks(int dtype_is_f64, int nt, int full, int device);
 template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
                          hipStream_t s);
+
+// b^ = sigma_m F^ in place on instance inst's tiled tau-spectrum (n = M n_y
+// elements): the flux difference applied to a tau-pass result.
+template <typename T>
+hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, hipStream_t s);
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,

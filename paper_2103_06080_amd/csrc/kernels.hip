@@ -407,7 +407,10 @@ __device__ __forceinline__ void r2c_post_prog(const cpx<T>* lds, int base, cpx<T
     }
 }
 
-// MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B (b via WENO5).
+// MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B, the
+// tau-spectrum of the WENO5 face fluxes F_{i+1/2} (the flux difference
+// b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau is the Fourier multiplier
+// sigma_m = -(1 - e^{-2 pi i m / n_tau}) / dtau, applied by the y-pass).
 // MODE 3: as MODE 2, and also stores the physical line u (for the adjoint).
 // PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width and
 // of 16 in every instance (progression indexing of the pre/post-processing
@@ -529,31 +532,6 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __rest
         }
     }
     __syncthreads();
-    // b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau
-    const T mdt = -(T)(1.0 / d.dtau);
-    #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int g = t + q * tpr;
-        if (active) {
-            T prev = lds_quad(lds, base, (2 * g - 1) & (Nc - 1)).v[3];
-            #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const T f = F[q][i];
-                F[q][i] = mdt * (f - prev);
-                prev = f;
-            }
-        }
-    }
-    __syncthreads();
-    #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int g = t + q * tpr;
-        if (active) {
-            lds_quad_st(lds, base, 2 * g, quad<T>{{F[q][0], F[q][1], F[q][2], F[q][3]}});
-            lds_quad_st(lds, base, 2 * g + 1, quad<T>{{F[q][4], F[q][5], F[q][6], F[q][7]}});
-        }
-    }
-    __syncthreads();
     lds_fft<T, -1>(lds, base, M, t, active, twst);
     if (active) {
         if constexpr (PROG) r2c_post_prog(lds, base, Bout + d.off_state, (unsigned)row << d.log2W, ix, M, t, tpr, tw,
@@ -607,6 +585,14 @@ __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, 
         return;
     }
     phis_closed_f64(zr, zi, e, p1, p2);
+}
+
+// Flux-difference symbol of tau-mode m (the table built at create, see
+// InstDesc::sigma): the spectrum of b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau is
+// sigma_m times that of F_{i+1/2}.
+template <typename T>
+__device__ __forceinline__ cpx<T> flux_diff_symbol(const InstDesc& d, int m) {
+    return static_cast<const cpx<T>*>(d.sigma)[m];
 }
 
 // Multipliers of mode (m, n) for step `step` (tau-mode m >= 1, |ky index| n),
@@ -772,6 +758,9 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     const int s0 = colbase(c) + padi(j0);               // slot of row j0 (q = 0)
     const int s1 = colbase(c) + padi(Ny - j0);          // slot of row Ny - j0 (q = 0)
     const bool keep_c = !(col0 && c == 0);
+    // the tau-pass leaves the spectrum of the face fluxes; b^ = sigma F^ (the
+    // column of a thread's combine items is tid mod W in both paths)
+    const cpx<T> sg = STAGE > 0 ? flux_diff_symbol<T>(d, m0 + c) : cpx<T>{(T)0, (T)0};
     cpx<T>* fbuf = FULL ? lds + colbase(fc) : lds;      // this thread's FFT column
     const int fbase = FULL ? 0 : fc * Ny;
 
@@ -861,14 +850,14 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     buf_st<T>(rP2, vself(q), q * NT * E, P2);
                     {
                         const int li = s0 + q * sq;
-                        const cpx<T> bh = lds[li];
+                        const cpx<T> bh = cmul(sg, lds[li]);
                         const cpx<T> EU = cmul(E0, u0);
                         if (keep_c) buf_st<T>(rP, vself(q), q * NT * E, EU + cmul(P1 - P2, bh));
                         lds[li] = EU + cmul(P1, bh);
                     }
                     if (two) {
                         const int li = s1 - q * sq;
-                        const cpx<T> bh = lds[li];
+                        const cpx<T> bh = cmul(sg, lds[li]);
                         const cpx<T> EU = cmul(E0, u1);
                         if (keep_c) buf_st<T>(rP, vpart(q), spart(q), EU + cmul(P1 - P2, bh));
                         lds[li] = EU + cmul(P1, bh);
@@ -908,7 +897,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                         const int li = pass ? s1 - qq * sq : s0 + qq * sq;
                         const unsigned vv = pass ? vpart(qq) : vself(qq);
                         const unsigned ss = pass ? spart(qq) : (unsigned)qq * NT * E;
-                        const cpx<T> bh = lds[li];
+                        const cpx<T> bh = cmul(sg, lds[li]);
                         if (STAGE == 1) {
                             const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
                             if (keep_c) buf_st<T>(rP, vv, ss, EU + cmul(tb[q][1] - tb[q][2], bh));
@@ -965,7 +954,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     if (pass == 1 && !two) break;
                     const int j = pass ? Ny - n : n;
                     const int e = j * W + cc, li = padi(cc * Ny + j);
-                    const cpx<T> bh = lds[li];
+                    const cpx<T> bh = cmul(sg, lds[li]);
                     const cpx<T> EU = cmul(E, pass ? u1 : u0);
                     if (keep_col) Pt[e] = EU + cmul(P1 - P2, bh);
                     lds[li] = EU + cmul(P1, bh);
@@ -1008,7 +997,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 if (pass == 1 && !two) break;
                 const int j = pass ? Ny - n : n;
                 const int e = j * W + cc, li = padi(cc * Ny + j);
-                const cpx<T> bh = lds[li];
+                const cpx<T> bh = cmul(sg, lds[li]);
                 if (STAGE == 1) {
                     const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
                     if (keep_col) Pt[e] = EU + cmul(tb[q][1] - tb[q][2], bh);
@@ -1046,9 +1035,10 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             P1N = tP1[0].x;
             P2N = tP2[0].x;
         }
+        const T sN = (T)(-2.0 / d.dtau);                  // sigma at the tau-Nyquist mode
         for (int y = tid; y < Ny; y += NT) {
             const long long o = (long long)y * W;
-            const cpx<T> b = Bt[o];
+            const cpx<T> b = {(T)0, sN * Bt[o].y};          // the DC of b is zero
             if (STAGE == 1) {
                 const cpx<T> cr = Ut[o];
                 Ct[o] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
@@ -1556,6 +1546,31 @@ hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const Y
                                           step, s);
 }
 
+// b^ = sigma F^ in place on one instance's tiled tau-spectrum (element e of
+// the instance: tile e / (W n_y), column e mod W, so tau-mode
+// m = (e / (W n_y)) W + e mod W; slot m = 0 holds (DC, Nyquist)).
+template <typename T>
+__global__ __launch_bounds__(256) void flux_diff_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                        cpx<T>* __restrict__ X) {
+    const InstDesc& d = descs[inst];
+    const long long n = (long long)d.M * d.n_y, tile = (long long)d.W * d.n_y;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int m = (int)((e / tile) * d.W + (e & (d.W - 1)));
+        cpx<T>& x = X[d.off_state + e];
+        if (m == 0) x = cpx<T>{(T)0, (T)(-2.0 / d.dtau) * x.y};
+        else x = cmul(flux_diff_symbol<T>(d, m), x);
+    }
+}
+
+template <typename T>
+hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    dim3 g((unsigned)(blocks < 4096 ? blocks : 4096)), b(256);
+    hipLaunchKernelGGL((flux_diff_kernel<T>), g, b, 0, s, d_desc, inst, static_cast<cpx<T>*>(X));
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
                          hipStream_t s) {
@@ -1642,6 +1657,7 @@ void stage_twiddles(double* out) {
     template hipError_t launch_y<T>(int, int, int, const InstDesc*, const YItem*, int, int, void*, const void*,     \
                                     void*, void*, void*, const void*, int, hipStream_t);                             \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
+    template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, hipStream_t);                    \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
                                           hipStream_t);                                                              \
