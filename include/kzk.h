@@ -166,7 +166,9 @@ const char *kzk_status_str(kzk_status s);
 
 /* b = -nl d_tau(u^2/2) by WENO5/LF on every tau-line of u_dev, with
  * nl = nl(x_node) (Sec. 3.4): b_dev receives the physical field b.  Runs the
- * production tau-pass kernel between a forward and an inverse tau-transform. */
+ * production tau-pass kernel (which leaves the tau-spectrum of the face
+ * fluxes) between a forward transform and, after the flux-difference
+ * multiplier sigma_m = -(1 - e^{-2 pi i m / n_tau}) / dtau, an inverse one. */
 kzk_status kzk_eval_b(kzk_plan *plan, const void *u_dev, int32_t node, void *b_dev);
 
 /* Forward tau-transform of the physical field (R2C along tau, packed: slot 0
