@@ -867,11 +867,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 u1 = x1;
             }
         } else {
+            // the loads of three items are issued before use (nine at once
+            // need more registers than the held twiddles leave; reloading the
+            // twiddles per transform to make room measured much slower)
+            constexpr int QB = 3;
             #pragma unroll
-            for (int q0 = 0; q0 < QH; q0 += 3) {
-                cpx<T> tb[3][3], ua[3][2];
+            for (int q0 = 0; q0 < QH; q0 += QB) {
+                cpx<T> tb[QB][3], ua[QB][2];
                 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
+                for (int q = 0; q < QB; ++q) {
                     const int qq = q0 + q;
                     const unsigned vs = vself(qq), ss = qq * NT * E;
                     if (STAGE == 1) {
@@ -887,7 +891,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     }
                 }
                 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
+                for (int q = 0; q < QB; ++q) {
                     const int qq = q0 + q;
                     if (!(qq < 8 || first)) continue;
                     const bool two = qq > 0 ? qq < 8 : !first;
@@ -1017,9 +1021,14 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     lds_fft_held<T, 1>(fbuf, fbase, Ny, ft, act, ytw);
     if constexpr (FULL) {
         const auto rc = buf_rsrc(Ct);
+        // an opaque copy of the base slot, so that the compiler recomputes the
+        // 16 slots here instead of keeping those of the tile load live in
+        // registers through both transforms and the combine
+        int sb = s0;
+        asm volatile("" : "+v"(sb));
         if (keep_c) {
             #pragma unroll
-            for (int q = 0; q < 16; ++q) buf_st<T>(rc, tid * E, q * NT * E, lds[s0 + q * sq]);
+            for (int q = 0; q < 16; ++q) buf_st<T>(rc, tid * E, q * NT * E, lds[sb + q * sq]);
         }
     } else {
         tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
