@@ -1546,9 +1546,6 @@ hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const Y
                     int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
                     hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    // the FP32 stage-1 kernel (multipliers evaluated per mode) measured
-    // slower in the full-tile form; it keeps the general one
-    if (sizeof(T) == 4 && stage == 1) full = 0;
     return full ? launch_y_full<T, true>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
                                          step, s)
                 : launch_y_full<T, false>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
