@@ -70,6 +70,22 @@ def test_weno_b_matches_oracle(torch_cuda, orc, dtype, nt, ny):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shapes", [[(64, 16), (512, 32), (2048, 16), (256, 64)],
+                                    [(512, 1024), (1024, 512), (4096, 128)]])
+def test_weno_b_of_a_batched_plan_matches_oracle(torch_cuda, orc, dtype, shapes):
+    """b of every solve of a plan of uneven grids: each solve's flux-difference
+    symbols (its own n_tau and dtau) and tile layout; the second set has
+    M >= 256 and M/16 >= W in every solve (progression-indexed tau-pass)."""
+    from paper_2103_06080_amd import kzk
+    probs = [small(nt, ny, nl=0.7, seed=i) for i, (nt, ny) in enumerate(shapes)]
+    plan = kzk.Plan(probs, dtype=dtype)
+    b = plan.eval_b(plan.pack([p.u0 for p in probs]), 0)
+    for p, got in zip(probs, plan.unpack(b)):
+        ref = np.stack([orc.weno_b(p.u0[j], p.dtau, 0.7, 0.7 * np.abs(p.u0[j]).max()) for j in range(p.n_y)])
+        assert rel_l2(got, ref) < (1e-12 if dtype == "f64" else max(2e-5, 2.5e-8 * p.n_tau)), (p.n_tau, p.n_y)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("nt,ny,n_steps,A", [(64, 16, 1, 0.0), (256, 128, 10, 1e-3), (128, 256, 5, 0.0),
                                              (512, 64, 7, 2e-4), (32, 4096, 2, 0.0), (8192, 32, 2, 1e-4),
                                              (512, 1024, 3, 1e-4), (2048, 1024, 2, 1e-4)])
