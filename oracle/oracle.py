@@ -5,6 +5,7 @@ leg of the benchmark may import this module; the product path never does.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -17,14 +18,14 @@ _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, OpenMP over independent lines)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Cfg(ctypes.Structure):
@@ -43,27 +44,45 @@ class _Cfg(ctypes.Structure):
     ]
 
 
+@contextlib.contextmanager
+def using_library(path: str):
+    """Run the functions of this module on another build of the oracle (the
+    mutation checks of the test-suite load copies with planted mistakes)."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_fft.argtypes = [dp, ctypes.c_int, ctypes.c_int]
-        L.orc_fft2.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-        L.orc_phi.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
-        L.orc_symbol.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
-        L.orc_weno_b.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_double, dp]
-        L.orc_weno_b_adj.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, dp, dp, dp]
-        L.orc_run.argtypes = [ctypes.POINTER(_Cfg), dp, ctypes.c_int, ctypes.c_int]
-        L.orc_run.restype = ctypes.c_int
-        L.orc_adjoint.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-        L.orc_adjoint.restype = ctypes.c_int
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def _load(path: str):
+    """Load one build of the oracle and declare its functions."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_fft.argtypes = [dp, ctypes.c_int, ctypes.c_int]
+    L.orc_fft2.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.orc_phi.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+    L.orc_symbol.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+    L.orc_weno_b.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, dp]
+    L.orc_weno_b_adj.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, dp, dp, dp]
+    L.orc_run.argtypes = [ctypes.POINTER(_Cfg), dp, ctypes.c_int, ctypes.c_int]
+    L.orc_run.restype = ctypes.c_int
+    L.orc_adjoint.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.orc_adjoint.restype = ctypes.c_int
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -146,9 +165,9 @@ def run(p, n_steps=None, first=0, u=None, lf_global=None, force0=None, force1=No
     return a
 
 
-def adjoint(p, lam_end: np.ndarray, n_steps=None, ckpt=50, u0=None, first=0) -> np.ndarray:
+def adjoint(p, lam_end: np.ndarray, n_steps=None, ckpt=50, u0=None, first=0, lf_global=None) -> np.ndarray:
     ns = p.n_steps if n_steps is None else n_steps
-    c = Cfg(p, n_steps=first + ns)
+    c = Cfg(p, n_steps=first + ns, lf_global=lf_global)
     u = np.ascontiguousarray(p.u0 if u0 is None else u0, dtype=np.float64)
     lam = np.ascontiguousarray(lam_end, dtype=np.float64).copy()
     rc = lib().orc_adjoint(ctypes.byref(c.c), _dp(u), _dp(lam), first, ns, ckpt)

@@ -185,11 +185,13 @@ def c2(seed: int = 0, n_steps: int = 1000, n_tau: int = 4096, n_y: int = 2048) -
 
 def c3_coefficients(h: float, n_steps: int, x0: float = 0.0):
     """nl at the nodes x_n and the step average of D(x) = 0.02 (1 + 0.3 sin x)
-    over [x_n, x_n + h] (closed-form integral of the sine)."""
+    over [x_n, x_n + h]: the integral of the sine, (cos x_n - cos(x_n + h)) / h,
+    written as the product 2 sin(x_n + h/2) sin(h/2) / h, which does not cancel
+    for small h."""
     xn = x0 + h * np.arange(n_steps + 1)
     nl = 1.0 + 0.5 * np.tanh(xn - 2.0)
     xs = xn[:-1]
-    Dbar = 0.02 * (1.0 + 0.3 * (np.cos(xs) - np.cos(xs + h)) / h)
+    Dbar = 0.02 * (1.0 + 0.3 * 2.0 * np.sin(xs + 0.5 * h) * np.sin(0.5 * h) / h)
     return Dbar, nl
 
 

@@ -124,6 +124,23 @@ def test_linear_part_exact_on_gaussian(orc, m0, h, n_steps):
     assert rel_l2(wrong, ref) > 1e-3
 
 
+def test_linear_part_exact_with_x_dependent_diffraction(orc):
+    """nl = 0 with a step schedule D_n: the multipliers of step n use D_n, so
+    after n steps the Gaussian follows the closed form with the accumulated
+    sum_n h D_n in place of D x (and absorption exp(-A k^2 x))."""
+    s, m0, h, ns = 1.0, 2, 0.05, 30
+    p = small_problem(nt=32, ny=256, h=h, n_steps=ns, D=0.05, nl=0.0, A=1e-3)
+    p.D_step = 0.05 * (1 + 0.8 * np.sin(0.7 * np.arange(ns)))
+    tau, y = p.tau(), p.y()
+    k = 2 * math.pi * m0 / p.L_tau
+    p.u0 = np.cos(k * tau)[None, :] * np.exp(-y ** 2 / (2 * s * s))[:, None]
+    u = orc.run(p)
+    c = s * s - 1j * float(h * p.D_step.sum()) / k
+    ref = math.exp(-p.A * k * k * h * ns) * np.real(
+        np.exp(1j * k * tau)[None, :] * (s / np.sqrt(c)) * np.exp(-y ** 2 / (2 * c))[:, None])
+    assert rel_l2(u, ref) < 1e-12
+
+
 # --------------------------------------------------------------------------- P4 absorption
 
 @pytest.mark.parametrize("m0", [3, 32])   # 32 = the tau-Nyquist index for nt = 64
@@ -431,3 +448,56 @@ def test_mean_tau_mode_of_b_is_zeroed(orc):
     u = orc.run(p, force0=f0, force1=f1)
     assert np.abs(u.mean(axis=1) - p.u0.mean(axis=1)).max() < 1e-14
     assert np.abs(u - p.u0).max() > 0.05
+
+
+# --------------------------------------------------------------------------- LF speed over the field
+
+def test_field_wide_lf_speed_reduces_to_heun_with_the_global_maximum(orc):
+    """lf_scope = 1 (one Lax-Friedrichs speed for the whole field, the
+    Jiang-Shu original): with D = 0 the step is Heun per line with
+    alpha = |nl| max over all lines of |u| at each stage.  Rows of different
+    amplitude make the per-line and field-wide speeds differ."""
+    nl = -0.9
+    p = small_problem(nt=64, ny=4, h=2e-3, n_steps=5, D=0.0, nl=nl)
+    p.u0 = I.random_field(17, (4, 64)) * np.array([1.0, 0.3, 2.0, 0.6])[:, None]
+    u = orc.run(p, lf_global=1)
+    v = p.u0.copy()
+    for _ in range(5):
+        a0 = abs(nl) * np.abs(v).max()
+        b0 = np.stack([orc.weno_b(v[j], p.dtau, nl, a0) for j in range(4)])
+        us = v + p.h * b0
+        a1 = abs(nl) * np.abs(us).max()
+        b1 = np.stack([orc.weno_b(us[j], p.dtau, nl, a1) for j in range(4)])
+        v = v + p.h * 0.5 * (b0 + b1)
+    assert np.abs(u - v).max() < 1e-13
+    assert np.abs(orc.run(p, lf_global=0) - v).max() > 1e-6   # the per-line speed differs
+
+
+def test_field_wide_lf_speed_adjoint_matches_central_differences(orc):
+    nt, ny, ns = 32, 8, 5
+    p = small_problem(nt=nt, ny=ny, h=4e-3, n_steps=ns, D=0.05, nl=1.0, A=1e-3)
+    p.u0 = I.random_field(33, (ny, nt)) * (1 + 0.5 * np.arange(ny))[:, None] / ny
+    w = I.random_field(34, (ny, nt))
+    grad = orc.adjoint(p, w, ckpt=2, lf_global=1)
+    eps = 1e-6
+    for r in range(3):
+        d = I.random_field(60 + r, (ny, nt))
+        up = orc.run(p, u=p.u0 + eps * d, lf_global=1)
+        um = orc.run(p, u=p.u0 - eps * d, lf_global=1)
+        fd = (w * (up - um)).sum() / (2 * eps)
+        assert abs(fd - (grad * d).sum()) < 1e-7 * abs(fd), (fd, (grad * d).sum())
+
+
+# --------------------------------------------------------------------------- x-dependent coefficients
+
+def test_inhomogeneous_coefficient_schedule_against_quadrature():
+    """The step coefficients of the inhomogeneous workload: nl(x_n) at the
+    nodes and the step average of D(x) = 0.02 (1 + 0.3 sin x) over
+    [x_n, x_n + h], here by 64-point Gauss-Legendre quadrature of D."""
+    for h, ns, x0 in ((2.5e-4, 2000, 0.0), (0.3, 40, 1.7)):
+        Dbar, nl = I.c3_coefficients(h, ns, x0)
+        xn = x0 + h * np.arange(ns + 1)
+        D = lambda x: 0.02 * (1 + 0.3 * np.sin(x))
+        ref = np.array([I_avg(D, x, h) for x in xn[:-1]])
+        assert np.abs(Dbar - ref).max() <= 1e-15 * 0.026   # a few units of rounding
+        assert np.abs(nl - (1 + 0.5 * np.tanh(xn - 2))).max() <= 4e-16
