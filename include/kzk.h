@@ -161,6 +161,28 @@ void kzk_destroy(kzk_plan *plan);
 
 const char *kzk_status_str(kzk_status s);
 
+/* ---- march without device allocation ----
+ * For callers that cannot allocate device memory (code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * kzk_step_noalloc(params, n_inst, hip_stream, u_dev, first_step, n_steps)
+ * does what kzk_create + kzk_step + kzk_poll + kzk_destroy do, with the same
+ * kernels and results, but takes all of its device memory (spectral state,
+ * stage arrays, multiplier and twiddle tables, work lists, status word) from
+ * one static device array of KZK_NOALLOC_SCRATCH_BYTES per GPU, which that
+ * GPU holds from the library's load until the process ends.  It calls no
+ * hipMalloc or hipFree.  Arguments as for kzk_create and kzk_step; u_dev is
+ * caller-owned.  Returns KZK_ERR_SIZE when the solves do not fit the array
+ * (about 2^20 grid points in FP32, 2^19 in FP64), the errors of kzk_create /
+ * kzk_step for invalid arguments, else the device status (KZK_OK,
+ * KZK_ERR_CFL or KZK_ERR_NONFINITE).  Synchronises the stream before it
+ * returns.  Every call on one GPU uses that GPU's array and overwrites what
+ * the last call left there: calls that overlap on one GPU (from several host
+ * threads) race and must not be made. */
+#define KZK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+kzk_status kzk_step_noalloc(const kzk_params *params, int32_t n_inst, void *hip_stream, void *u_dev,
+                            int32_t first_step, int32_t n_steps);
+
 /* ---- single-operator entry points (used for per-kernel parity) ----
  * Each applies one piece of the step to every solve of the plan. */
 

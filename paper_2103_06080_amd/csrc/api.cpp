@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -55,6 +56,10 @@ struct kzk_plan {
     unsigned* dStatus = nullptr;
     double* dSched = nullptr;
     std::vector<void*> owned;             // everything hipMalloc'ed, freed in destroy
+    // plans of kzk_step_noalloc carve their device memory out of the static
+    // scratch array instead (bump allocation, nothing to free)
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
 
     bool graph_on = false;
     hipGraphExec_t gexec = nullptr;
@@ -80,6 +85,13 @@ namespace {
 kzk_status dev_alloc(kzk_plan* p, void** out, size_t bytes) {
     *out = nullptr;
     if (bytes == 0) bytes = 256;
+    if (p->arena) {
+        const size_t off = (p->arena_used + 255) & ~(size_t)255;
+        if (off > p->arena_cap || bytes > p->arena_cap - off) return KZK_ERR_SIZE;
+        *out = p->arena + off;
+        p->arena_used = off + bytes;
+        return KZK_OK;
+    }
     if (hipMalloc(out, bytes) != hipSuccess) {
         (void)hipGetLastError();
         *out = nullptr;
@@ -309,7 +321,14 @@ void kzk_destroy(kzk_plan* p) {
     delete p;
 }
 
-kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream, kzk_plan** out) {
+}  // extern "C"
+
+namespace {
+
+// kzk_create, with the device memory taken from [arena, arena + arena_cap)
+// when arena is not null (KZK_ERR_SIZE if it does not fit there).
+kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_stream, char* arena, size_t arena_cap,
+                       kzk_plan** out) {
     if (!out) return KZK_ERR_ARG;
     *out = nullptr;
     if (!params || n_inst < 1) return KZK_ERR_ARG;
@@ -320,6 +339,8 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
     }
     kzk_plan* p = new (std::nothrow) kzk_plan();
     if (!p) return KZK_ERR_OOM;
+    p->arena = arena;
+    p->arena_cap = arena ? arena_cap : 0;
     p->n_inst = n_inst;
     p->dtype = params[0].dtype;
     p->esz = p->dtype == KZK_F32 ? 4 : 8;
@@ -484,6 +505,14 @@ kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream
     if (hipStreamSynchronize(p->stream) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     *out = p;
     return KZK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kzk_status kzk_create(const kzk_params* params, int32_t n_inst, void* hip_stream, kzk_plan** out) {
+    return create_plan(params, n_inst, hip_stream, nullptr, 0, out);
 }
 
 kzk_status kzk_set_stream(kzk_plan* p, void* s) {
@@ -772,3 +801,53 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
     return KZK_OK;
 }
 
+
+// ------------------------------------------------------------------ march without allocation
+// Device memory of kzk_step_noalloc: one array per GPU (each device holds its
+// own copy from the library's load on that device until the process ends).
+// Host code never passes the array's name to a kernel or a copy: it takes the
+// device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[KZK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device.
+kzk_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        (void)hipGetLastError();
+        return KZK_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return KZK_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return KZK_OK;
+}
+
+}  // namespace
+
+extern "C" kzk_status kzk_step_noalloc(const kzk_params* params, int32_t n_inst, void* hip_stream, void* u_dev,
+                                       int32_t first_step, int32_t n_steps) {
+    if (!params || !u_dev || n_inst < 1) return KZK_ERR_ARG;
+    void* base = nullptr;
+    kzk_status st = scratch_address(&base);
+    if (st != KZK_OK) return st;
+    kzk_plan* p = nullptr;
+    st = create_plan(params, n_inst, hip_stream, static_cast<char*>(base), KZK_NOALLOC_SCRATCH_BYTES, &p);
+    if (st != KZK_OK) return st;
+    st = kzk_step(p, u_dev, first_step, n_steps);
+    const kzk_status ps = kzk_poll(p);   // synchronises: the scratch is free again on return
+    kzk_destroy(p);
+    return st != KZK_OK ? st : ps;
+}

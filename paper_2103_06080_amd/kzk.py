@@ -22,7 +22,7 @@ STATUS = {0: "KZK_OK", 1: "KZK_ERR_ARG", 2: "KZK_ERR_SIZE", 3: "KZK_ERR_OOM", 4:
 EXPORTS = ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_inst_offset", "kzk_set_stream",
            "kzk_set_graph", "kzk_set_y_threads", "kzk_get_y_threads", "kzk_destroy", "kzk_status_str",
            "kzk_eval_b", "kzk_tau_forward", "kzk_tau_inverse", "kzk_profile_enable", "kzk_profile_read",
-           "kzk_read_tables", "kzk_autotune"]
+           "kzk_read_tables", "kzk_autotune", "kzk_step_noalloc"]
 KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "other"]
 
 
@@ -83,6 +83,7 @@ def lib():
         L.kzk_read_tables.argtypes = [vp, i32, vp]
         L.kzk_autotune.argtypes = [vp, vp, i32]
         L.kzk_autotune.restype = i32
+        L.kzk_step_noalloc.argtypes = [ctypes.POINTER(Params), i32, vp, vp, i32, i32]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -121,6 +122,20 @@ def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None
                   float(p.D_const if p.D_const is not None else 0.0), p.A,
                   float(p.nl_const if p.nl_const is not None else 0.0),
                   D_ptr, nl_ptr, nmax, p.lf_scope, p.weno_eps, cfl_max)
+
+
+def step_noalloc(problems, u, first: int = 0, n_steps: int = 1, dtype: str = "f64", stream=None,
+                 cfl_max: float = 1.0) -> int:
+    """kzk_step_noalloc: march the packed field u (laid out as a Plan of the
+    same problems packs it) without any device allocation; returns the status
+    code (0 = ok; synchronises)."""
+    if not isinstance(problems, (list, tuple)):
+        problems = [problems]
+    dt = KZK_F32 if dtype in ("f32", "float32") else KZK_F64
+    keep: list = []
+    arr = (Params * len(problems))(*[make_params(p, dt, cfl_max, keep) for p in problems])
+    return lib().kzk_step_noalloc(arr, len(problems), ctypes.c_void_p(_stream_handle(stream)),
+                                  ctypes.c_void_p(u.data_ptr()), int(first), int(n_steps))
 
 
 class Plan:
