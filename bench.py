@@ -5,12 +5,14 @@ One bench "step" is one pass of the whole hot path over one batch of
 synthetic input: the full inhomogeneous-medium march of an 8192 x 4096
 (tau x y) N-wave, 2000 ExpRK22 steps with x-dependent nl(x), D(x) and
 absorption, in FP32 (the FP64 multipliers of each step evaluated in the first y-pass).
-Consecutive bench steps continue the march (steps k*2000 .. (k+1)*2000-1),
-so every timed step does identical work on a field resident in HBM.
+Every bench step is that march from its initial field (x from 0 to 0.5),
+copied from a resident copy in HBM, so every timed step does identical work.
 
 Prints one JSON line: value = grid-point-steps per second, plus the
 roofline of the dominant kernel (per-kernel HIP events over the timed
-region) and the FP64 CPU oracle timed on a bounded sample.
+region), the error against the FP64 oracle (first steps of the workload on
+the whole field; the full march on the stored oracle rows) and the FP64 CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -24,7 +26,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 PROFILE_EVERY = 8              # per-kernel HIP events on every 8th step of the timed marches
-ALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}   # vector FMA without packed FP32 (256 CU x 64 lanes x 2 x 2.4 GHz)
+# MI355X published vector peaks (FP32 counts packed FP32 instructions)
+ALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# issue rate of the instructions this build uses (no packed FP32):
+# 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz, the same in FP32 and FP64
+NONPACKED_PEAK_TFLOPS = 78.6
+ORACLE_STEPS = 4               # steps of the oracle sample (CPU baseline and first-steps parity)
 
 WORKLOADS = {
     # name: (builder, default dtype)
@@ -77,17 +84,61 @@ def pmc_traffic(kernel_kind, workload, dtype):
         return None
 
 
-def cpu_baseline(problem):
-    """The FP64 oracle, as it stands, on one ExpRK22 step of the same grid."""
+def cpu_baseline(problem, n_steps=ORACLE_STEPS):
+    """The FP64 oracle, as it stands, on the first n_steps ExpRK22 steps of the
+    same workload; the rate counts the step loop only (each step with its
+    FP64 multiplier build), not the transforms at the ends of the run.
+    Returns the record and the oracle's field after the steps."""
     from oracle import oracle
     oracle.lib()
     t0 = time.perf_counter()
-    oracle.run(problem, n_steps=1)
-    dt = time.perf_counter() - t0
+    ref = oracle.run(problem, n_steps=n_steps)
+    total = time.perf_counter() - t0
+    dt = oracle.last_step_seconds()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": problem.points / dt, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "1 ExpRK22 step of the %d x %d grid (incl. its FP64 multiplier build and the initial "
-                      "and final 2D transforms), %.1f s" % (problem.n_tau, problem.n_y, dt)}
+    rec = {"value": problem.points * n_steps / dt, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
+           "sample": "the first %d ExpRK22 steps of the %d x %d workload (its FP64 multipliers rebuilt every "
+                     "step); step loop %.1f s of a %.1f s run that also holds the two 2D transforms"
+                     % (n_steps, problem.n_tau, problem.n_y, dt, total)}
+    return rec, ref
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def first_steps_error(problem, ref, dtype, n_steps=ORACLE_STEPS):
+    """GPU march of the same first steps against the oracle's (rel. l2 over
+    the field, and the largest pointwise error over max|u|)."""
+    import numpy as np
+    from paper_2103_06080_amd import kzk
+    plan = kzk.Plan(problem, dtype=dtype)
+    u = plan.pack([problem.u0])
+    plan.step(u, 0, n_steps)
+    assert plan.poll() == 0
+    got = plan.unpack(u)[0]
+    plan.close()
+    return {"steps": n_steps, "rel_l2": rel_l2(got, ref),
+            "max_err_over_max_u": float(np.abs(got - ref).max() / np.abs(ref).max())}
+
+
+def sampled_march_error(name, u_host, n_steps):
+    """Rows of a full march against the stored oracle rows of the same march
+    (tests/golden, written by a script that calls only the oracle)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "%s_seed0_oracle_rows.npz" % name)
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    key = "u_step%d" % n_steps
+    if key not in z.files:
+        return None
+    rows = z["rows_final"]
+    ref = z[key]
+    got = u_host[rows]
+    return {"steps": n_steps, "rows": len(rows), "of_rows": int(u_host.shape[0]), "rel_l2": rel_l2(got, ref),
+            "max_err_over_max_u": float(np.abs(got - ref).max() / np.abs(ref).max())}
 
 
 def _time(fn, sync):
@@ -102,21 +153,29 @@ def side_measurements(args, value_fp32, ms_fp32):
     """FP64 march of the same workload, the adjoint/forward time ratio on the
     2048 x 1024 adjoint workload, and the batched 64-solve throughput."""
     import torch
-    from paper_2103_06080_amd import autograd, inputs, kzk
+    from paper_2103_06080_amd import inputs, kzk
     sync = torch.cuda.synchronize
     out = {}
-    # FP64, same march
-    p = inputs.c3(n_steps=2 * 2000)
+    # FP64, the same march (steps 0 .. 1999 from the initial field)
+    p = inputs.c3()
     plan = kzk.Plan(p, dtype="f64")
-    u = plan.pack([p.u0])
-    plan.step(u, 0, 2000)
-    t = _time(lambda: plan.step(u, 2000, 2000), sync)
+    u0 = plan.pack([p.u0])
+    u = u0.clone()
+    plan.step(u, 0, p.n_steps)
+
+    def fp64_march():
+        u.copy_(u0)
+        plan.step(u, 0, p.n_steps)
+    t = _time(fp64_march, sync)
     assert plan.poll() == 0
-    v64 = p.points * 2000 / t
-    out["fp64_c3"] = {"s_per_march": t, "value": v64, "fp32_speedup": value_fp32 / v64}
-    del plan, u
+    v64 = p.points * p.n_steps / t
+    out["fp64_c3"] = {"s_per_march": t, "value": v64, "fp32_speedup": value_fp32 / v64,
+                      "y_threads": plan.y_threads}
+    plan.close()
+    del plan, u, u0
     torch.cuda.empty_cache()
-    # adjoint / forward on the adjoint workload (FP32 and FP64)
+    # adjoint / forward on the adjoint workload (FP32 and FP64); its 8 / 16 MB
+    # arrays fit the 256 MB Infinity Cache, so these rates are cache-assisted
     q = inputs.c5()
     for dt in ("f32", "f64"):
         plan = kzk.Plan(q, dtype=dt)
@@ -130,23 +189,27 @@ def side_measurements(args, value_fp32, ms_fp32):
         ta = _time(lambda: plan.adjoint(u0, lam, 0, q.n_steps, inputs.C5_CKPT), sync)
         assert plan.poll() == 0
         out["adjoint_c5_" + dt] = {"fwd_s": tf, "adjoint_s": ta, "adjoint_over_fwd": ta / tf,
-                                   "ckpt_every": inputs.C5_CKPT}
+                                   "ckpt_every": inputs.C5_CKPT, "cache_assisted": True}
+        plan.close()
         del plan
     torch.cuda.empty_cache()
-    # batched: 64 uneven solves in one plan, the whole march replayed as one HIP graph
+    # batched: 64 uneven solves in one plan, autotuned, the whole march replayed as one HIP graph
     probs = inputs.c4()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        plan = kzk.Plan(probs, dtype="f32", stream=stream, graph=True)
+        plan = kzk.Plan(probs, dtype="f32", stream=stream)
         u = plan.pack([pp.u0 for pp in probs])
         u0 = u.clone()
+        tuned = plan.autotune(u, 3)
+        plan.set_graph(True)
         plan.step(u, 0, 500)
         u.copy_(u0)
         tb = _time(lambda: plan.step(u, 0, 500), stream.synchronize)
         assert plan.poll() == 0
     pts = sum(pp.points for pp in probs)
     out["batched_c4_f32"] = {"solves": len(probs), "points": pts, "s_per_march": tb,
-                             "value": pts * 500 / tb, "graph": True, "y_threads": plan.y_threads}
+                             "value": pts * 500 / tb, "graph": True, "autotuned": plan.tuning()}
+    plan.close()
     return out
 
 
@@ -160,6 +223,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--y-threads", type=int, default=0, help="y-pass block size (0: plan default)")
+    ap.add_argument("--tau-threads", type=int, default=0, help="tau-pass block size (0: plan default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for memory counters)")
     ap.add_argument("--march-steps", type=int, default=0, help="override the steps of one march (profiling)")
@@ -185,18 +249,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    base = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config]()
-    steps_per_march = args.march_steps or base.n_steps
-    total = steps_per_march * (args.warmup + args.steps)
-    prob = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config](n_steps=total)
+    make = {"c3": inputs.c3, "c2": inputs.c2, "c1": inputs.c1}[args.config]
+    prob = make()
+    steps_per_march = min(args.march_steps or prob.n_steps, prob.n_steps)
 
-    plan = kzk.Plan(prob, dtype=args.dtype, y_threads=args.y_threads or None)
-    u = plan.pack([prob.u0])
+    plan = kzk.Plan(prob, dtype=args.dtype, y_threads=args.y_threads or None, tau_threads=args.tau_threads or None)
+    u0 = plan.pack([prob.u0])
+    u = torch.empty_like(u0)
     torch.cuda.synchronize()
 
-    # warm-up marches
-    for w in range(args.warmup):
-        plan.step(u, w * steps_per_march, steps_per_march)
+    # every march (warm-up and timed) is the workload itself: steps 0 .. n-1
+    # from the initial field, which stays resident in HBM (the copy into the
+    # working field, 0.05 ms, is inside the timed region)
+    def one_march():
+        u.copy_(u0)
+        plan.step(u, 0, steps_per_march)
+
+    for _ in range(args.warmup):
+        one_march()
     st = plan.poll()
     if st != 0:
         raise SystemExit("device status %d during warm-up" % st)
@@ -206,7 +276,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        plan.step(u, (args.warmup + k) * steps_per_march, steps_per_march)
+        one_march()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = plan.profile_read() if not args.no_profile else {}
@@ -214,7 +284,7 @@ def main():
     st = plan.poll()
     if st != 0:
         raise SystemExit("device status %d in the timed region" % st)
-    u_host = u.double().cpu().numpy()
+    u_host = u.double().cpu().numpy().reshape(prob.n_y, prob.n_tau)
     assert np.isfinite(u_host).all()
 
     elapsed = t1 - t0
@@ -239,25 +309,35 @@ def main():
         else:
             roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS[args.dtype],
                         "unit": "TFLOP/s", "frac": round(tfl / ALU_PEAK_TFLOPS[args.dtype], 4)}
+        roofline["traffic"] = pmc_traffic(dom, args.config, args.dtype)
         roofline["kernel"] = dom
         roofline["avg_launch_us"] = round(avg_s * 1e6, 2)
         roofline["algorithmic_bytes_per_launch"] = nbytes
         roofline["algorithmic_flops_per_launch"] = nflops
         roofline["hbm_gbs_algorithmic"] = round(gbs, 1)
-        roofline["traffic"] = pmc_traffic(dom, args.config, args.dtype)
-        # whole-step model: 12 array transfers per ExpRK22 step
-        roofline["step_model_gbs"] = round(12 * esz * prob.points * steps_per_march * args.steps / elapsed / 1e9, 1)
+        roofline["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        roofline["alu_frac_of_nonpacked_rate"] = round(tfl / NONPACKED_PEAK_TFLOPS, 4)
+        # whole-step models: 11 array transfers per step (the minimal two-pass
+        # model) and the 12 this build moves (it also writes the spectral state)
+        step_bytes = esz * prob.points * steps_per_march * args.steps
+        roofline["step_model_11_gbs"] = round(11 * step_bytes / elapsed / 1e9, 1)
+        roofline["step_model_11_frac"] = round(11 * step_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["step_model_12_gbs"] = round(12 * step_bytes / elapsed / 1e9, 1)
 
-    y_threads = plan.y_threads
+    tuning = plan.tuning()
+    errors = {"full_march_sampled_rows": sampled_march_error(args.config, u_host, steps_per_march)}
+    plan.close()
+    del plan, u, u0
+    torch.cuda.empty_cache()
+
     extras = None
     if not args.no_extras and args.config == "c3" and not args.march_steps:
-        del plan, u
-        torch.cuda.empty_cache()
         extras = side_measurements(args, value, ms_per_step)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(base)
+        cpu, ref = cpu_baseline(prob)
+        errors["first_steps"] = {dt: first_steps_error(prob, ref, dt) for dt in ("f32", "f64")}
 
     line = {
         "metric": "grid-point-steps/s",
@@ -274,7 +354,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s, %s" % (args.config, WORKLOADS[args.config], args.dtype),
                    "n_tau": prob.n_tau, "n_y": prob.n_y, "march_steps": steps_per_march,
-                   "y_threads": y_threads, "parallelism": "single GPU"},
+                   "x_range": [prob.x0, prob.x0 + prob.h * steps_per_march],
+                   "tuning": tuning, "parallelism": "single GPU"},
+        "rel_l2_vs_oracle": errors,
         "roofline": roofline,
         "kernels": kernels,
         "extras": extras,

@@ -26,7 +26,8 @@
  *    (CFL limit exceeded, non-finite values) are latched in a device status
  *    word and reported by kzk_poll.
  *  - Multiplier conventions: the mean tau-mode has l = 0 (E = 1, Phi1 = 1,
- *    Phi2 = 1/2) and F(b)(0, .) = 0; at the tau-Nyquist index only the
+ *    Phi2 = 1/2) and F(b)(0, .) = 0, unless the regularised multiplier is
+ *    chosen (kzk_params.reg_eps); at the tau-Nyquist index only the
  *    absorption part of l is kept.
  */
 #ifndef KZK_H
@@ -72,6 +73,15 @@ typedef struct {
     int32_t lf_scope;       /* 0: LF speed per tau-line (only value supported)             */
     double weno_eps;        /* WENO epsilon (> 0), 1e-6 in the usual reading               */
     double cfl_max;         /* alpha h / dtau above this latches KZK_ERR_CFL (0 -> 1.0)    */
+    int32_t scheme;         /* 0: ExpRK22 (Sec. 3.3 eq. (19), Algorithm 2); 1: exponential
+                               Euler, u^{n+1} = E u^n + h phi1(hL) b(x_n, u^n) (Sec. 3.3);
+                               the same for every solve of a plan                           */
+    double reg_eps;         /* 0: mean tau-mode zeroed (l = 0 there and F(b)(0, .) = 0);
+                               > 0: the regularised multiplier of Sec. 3.4 (definition of
+                               z_jk): 1/(i k_tau) becomes 1/(i k_tau + reg_eps / (4 pi)) at
+                               every tau-mode, so the mean mode of every ky != 0 is damped
+                               by exp(-h (D/2) ky^2 4 pi / reg_eps); the paper takes the
+                               machine epsilon of the working precision                    */
 } kzk_params;
 
 /* Create a plan for n_inst independent solves (n_inst >= 1), params[i] for
@@ -95,7 +105,8 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * march, derived from Sec. 3.3 eq. (19)): given the field u0_dev at step
  * first_step and lam_dev = dL/du at step first_step + n_steps, write dL/du0
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
- * checkpoints taken every ckpt_every steps.  Asynchronous. */
+ * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
+ * with the mean mode zeroed (scheme 0, reg_eps 0); KZK_ERR_ARG otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 
@@ -120,16 +131,30 @@ kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
  * smallest size whose column tiles are at least 32 bytes wide. */
 kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
+/* Select the tau-pass block size: 256 threads (one 8192-point line per
+ * block), or 512 in FP32 only (two such lines, so the rows that share the
+ * 128-byte lines of the column-tiled spectra belong to fewer blocks).
+ * 0 restores the default (256). */
+kzk_status kzk_set_tau_threads(kzk_plan *plan, int32_t threads);
+
 /* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is
- * read, never written) for every supported y-pass block size, keep the
- * fastest and return it (> 0), or return -(kzk_status) on error.  The y-pass
- * block size fixes the column-tile width W = threads * 16 / n_y of the
- * y-FFTs and of the spectral layout (and so the row segments of the
- * tau-pass).  Synchronises. */
+ * read, never written) for every supported pair of y-pass and tau-pass block
+ * sizes, keep the fastest pair and return its y-pass block size (> 0), or
+ * -(kzk_status) on error.  The y-pass block size fixes the column-tile width
+ * W = threads * 16 / n_y of the y-FFTs and of the spectral layout (and so
+ * the row segments of the tau-pass); the tau-pass block size fixes how many
+ * tau-lines one block transforms and differentiates together.  If the
+ * environment variable KZK_TUNE_CACHE names a file, a plan whose key (device
+ * architecture, dtype, scheme, every solve's grid) is listed there takes the
+ * stored pair without timing, and a timed result is appended to it as the
+ * text line "<key> <y_threads> <tau_threads> <ms per step>".  Synchronises. */
 int32_t kzk_autotune(kzk_plan *plan, const void *u_dev, int32_t n_trial);
 
 /* Current y-pass block size. */
 int32_t kzk_get_y_threads(const kzk_plan *plan);
+
+/* Current tau-pass block size. */
+int32_t kzk_get_tau_threads(const kzk_plan *plan);
 
 /* Kernel classes reported by kzk_profile_read. */
 enum {

@@ -34,6 +34,7 @@
 
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -153,6 +154,16 @@ static double wavenumber(int idx, int npts, double len)
 
 static cplx symbol(const orc_cfg *c, int m, int n, double Dbar)
 {
+    if (c->reg_eps > 0) {
+        /* regularised Fourier multiplier (Sec. 3.4, definition of z_jk): the
+           antiderivative 1/(i kt) becomes 1/(i kt + eps/(4 pi)), which is
+           finite at kt = 0, so the mean tau-mode takes the same formula */
+        double kt = wavenumber(m, c->nt, c->Lt);
+        double ky = wavenumber(n, c->ny, c->Ly);
+        double absorb = -c->A * kt * kt;
+        if (2 * m == c->nt) return absorb;         /* tau-Nyquist: no diffraction */
+        return absorb - 0.5 * Dbar * ky * ky / (I * kt + c->reg_eps / (4.0 * PI));
+    }
     if (m == 0) return 0;                          /* mean mode zeroed */
     double kt = wavenumber(m, c->nt, c->Lt);
     double ky = wavenumber(n, c->ny, c->Ly);
@@ -315,12 +326,129 @@ static double max_abs(const double *u, size_t n)
     return m;
 }
 
-/* b = WENO5 Burgers term with coefficient nl, or the prescribed forcing. */
+/* ------------------------------------------------------------------------ */
+/* Random velocity field, Sec. 2 and Algorithm 1                             */
+/* ------------------------------------------------------------------------ */
+
+/* Wavenumbers K_n (1/m) and amplitudes |U~(K_n)| / c0 of the N modes:
+   K_n equispaced in [0.1/L, 9/L] with L = 4 lambda; Gaussian energy spectrum
+   E(K) = sigma_u^2 K^3 L^4 exp(-(K L/2)^2) / 8; |U~(K_n)| = sqrt(E(K_n)/N). */
+static void vel_spectrum(const orc_cfg *c, double *K, double *amp)
+{
+    int N = c->vel_modes;
+    double L = 4.0 * c->vel_lambda;
+    double kmin = 0.1 / L, kmax = 9.0 / L;
+    for (int n = 0; n < N; ++n) {
+        K[n] = N > 1 ? kmin + (kmax - kmin) * (double)n / (double)(N - 1) : kmin;
+        double E = 0.125 * sq(c->vel_sigma_u) * pow(K[n], 3) * pow(L, 4) * exp(-sq(K[n] * L / 2.0));
+        amp[n] = sqrt(E / (double)N) / c->vel_c0;
+    }
+}
+
+/* Algorithm 1 at (sigma, rho) = (x, y): with r = lambda (x, y) and
+   U~_n = |U~(K_n)| (-sin theta_n, cos theta_n),
+     U_par  = sum_n U~_{n,1} cos(K_n lambda |(x, y)| cos(theta_n - atan2(y, x)) + phi_n),
+     U_perp = sum_n U~_{n,2} cos(same phase),
+   and d_y U_perp from the derivative of the phase, which is K_n . r =
+   K_n lambda (x cos theta_n + y sin theta_n), so d phase / d y = K_n lambda sin theta_n. */
+static void vel_modal(const orc_cfg *c, const double *K, const double *amp, double x, double y, double out[3])
+{
+    double rad = c->vel_lambda * sqrt(x * x + y * y);
+    double ang = atan2(y, x);
+    double a = 0, p = 0, dp = 0;
+    for (int n = 0; n < c->vel_modes; ++n) {
+        double th = c->vel_theta[n];
+        double ph = K[n] * rad * cos(th - ang) + c->vel_phi[n];
+        double U1 = -amp[n] * sin(th), U2 = amp[n] * cos(th);
+        a += U1 * cos(ph);
+        p += U2 * cos(ph);
+        dp -= U2 * sin(ph) * K[n] * c->vel_lambda * sin(th);
+    }
+    out[0] = a;
+    out[1] = p;
+    out[2] = dp;
+}
+
+void orc_velocity(const orc_cfg *c, double x, double y, double out[3])
+{
+    out[0] = out[1] = out[2] = 0;
+    if (c->vel == 2) {
+        int j = (int)lround((y - c->y0) / (c->Ly / c->ny));
+        j = wrap(j, c->ny);
+        for (int k = 0; k < 3; ++k) out[k] = c->vel_prof[(size_t)k * c->ny + j];
+    } else if (c->vel == 1 && c->vel_modes > 0) {
+        double *K = (double *)malloc(sizeof(double) * c->vel_modes);
+        double *amp = (double *)malloc(sizeof(double) * c->vel_modes);
+        vel_spectrum(c, K, amp);
+        vel_modal(c, K, amp, x, y, out);
+        free(K);
+        free(amp);
+    }
+}
+
+/* b with transport, conservative form (Sec. 3.4 eq. (21)-(22)):
+     b = -d_tau f - d_y g + (d_y U_perp) u,  f = nl u^2/2 - 2 pi U_par u,  g = U_perp u,
+   each derivative a WENO5-JS flux difference with Lax-Friedrichs splitting
+   along its own lines: along tau with alpha = max_k |f'(u_k)| = max_k |nl u_k -
+   2 pi U_par(y_j)| per tau-line, along y with alpha = max_j |U_perp(y_j)| (the
+   same for every y-line, since g' = U_perp does not depend on u or tau). */
+static void eval_b_transport(const orc_cfg *c, double x, double nl, const double *u, double *b)
+{
+    int nt = c->nt, ny = c->ny;
+    double dtau = c->Lt / nt, dy = c->Ly / ny;
+    double *vel = (double *)malloc(sizeof(double) * 3 * ny);
+    for (int j = 0; j < ny; ++j) orc_velocity(c, x, c->y0 + dy * j, vel + 3 * j);
+    #pragma omp parallel
+    {
+        double *fp = (double *)malloc(sizeof(double) * (nt > ny ? nt : ny));
+        double *fm = (double *)malloc(sizeof(double) * (nt > ny ? nt : ny));
+        double *F = (double *)malloc(sizeof(double) * (nt > ny ? nt : ny));
+        #pragma omp for schedule(static)
+        for (int j = 0; j < ny; ++j) {
+            const double *uj = u + (size_t)j * nt;
+            double cpar = 2.0 * PI * vel[3 * j];
+            double alpha = 0;
+            for (int k = 0; k < nt; ++k) alpha = fmax(alpha, fabs(nl * uj[k] - cpar));
+            for (int k = 0; k < nt; ++k) {
+                double f = nl * uj[k] * uj[k] / 2.0 - cpar * uj[k];
+                fp[k] = 0.5 * (f + alpha * uj[k]);
+                fm[k] = 0.5 * (f - alpha * uj[k]);
+            }
+            for (int k = 0; k < nt; ++k) F[k] = lf_face(fp, fm, k, nt, c->eps);
+            for (int k = 0; k < nt; ++k) b[(size_t)j * nt + k] = -(F[k] - F[wrap(k - 1, nt)]) / dtau;
+        }
+        double ay = 0;
+        for (int j = 0; j < ny; ++j) ay = fmax(ay, fabs(vel[3 * j + 1]));
+        #pragma omp for schedule(static)
+        for (int k = 0; k < nt; ++k) {
+            for (int j = 0; j < ny; ++j) {
+                double v = u[(size_t)j * nt + k];
+                double g = vel[3 * j + 1] * v;
+                fp[j] = 0.5 * (g + ay * v);
+                fm[j] = 0.5 * (g - ay * v);
+            }
+            for (int j = 0; j < ny; ++j) F[j] = lf_face(fp, fm, j, ny, c->eps);
+            for (int j = 0; j < ny; ++j)
+                b[(size_t)j * nt + k] += -(F[j] - F[wrap(j - 1, ny)]) / dy + vel[3 * j + 2] * u[(size_t)j * nt + k];
+        }
+        free(fp);
+        free(fm);
+        free(F);
+    }
+    free(vel);
+}
+
+/* b = WENO5 Burgers term with coefficient nl (with the transport terms if
+   the configuration has a velocity field), or the prescribed forcing. */
 static void eval_b(const orc_cfg *c, double x, double nl, const double *u, double *b)
 {
     size_t N = (size_t)c->nt * c->ny;
     if (c->force0) {
         for (size_t i = 0; i < N; ++i) b[i] = c->force0[i] + x * c->force1[i];
+        return;
+    }
+    if (c->vel) {
+        eval_b_transport(c, x, nl, u, b);
         return;
     }
     double dtau = c->Lt / c->nt;
@@ -332,6 +460,8 @@ static void eval_b(const orc_cfg *c, double x, double nl, const double *u, doubl
         orc_weno_b(uj, c->nt, dtau, nl, fabs(nl) * m, c->eps, b + (size_t)j * c->nt);
     }
 }
+
+void orc_eval_b(const orc_cfg *c, double x, double nl, const double *u, double *b) { eval_b(c, x, nl, u, b); }
 
 /* Adjoint of eval_b at u (WENO case): u_bar = (db/du)^T g, including the
    dependence of alpha = |nl| max|u| on u (sub-gradient split over ties). */
@@ -418,11 +548,14 @@ static void to_physical(const cplx *U, double *u, cplx *W, int ny, int nt)
     for (size_t i = 0; i < N; ++i) u[i] = creal(W[i]) / (double)N;
 }
 
-/* F(b) with the mean tau-mode zeroed: B(0, n) := 0. */
-static void b_spectral(const double *b, cplx *B, int ny, int nt)
+/* F(b) with the mean tau-mode zeroed, B(0, n) := 0 (the unregularised
+   multiplier); the regularised multiplier treats the mean mode like every
+   other one and keeps it. */
+static void b_spectral(const orc_cfg *c, const double *b, cplx *B)
 {
-    to_spectral(b, B, ny, nt);
-    for (int n = 0; n < ny; ++n) B[(size_t)n * nt] = 0;
+    to_spectral(b, B, c->ny, c->nt);
+    if (c->reg_eps > 0) return;
+    for (int n = 0; n < c->ny; ++n) B[(size_t)n * c->nt] = 0;
 }
 
 typedef struct {
@@ -471,22 +604,33 @@ static void step(const orc_cfg *c, work *w, int s, double *un, double *ustar)
     to_physical(w->U, w->u, w->W, ny, nt);
     if (un) memcpy(un, w->u, sizeof(double) * N);
     eval_b(c, xn, c->nl[s], w->u, w->b);
-    b_spectral(w->b, w->B0, ny, nt);
+    b_spectral(c, w->b, w->B0);
 
     /* STEP 2: F(u*) = E F(u^n) + h Phi1 F(b^n) */
     cplx *Us = w->B1;   /* reuse storage until STEP 3 needs B1 */
     for (size_t i = 0; i < N; ++i) Us[i] = E[i] * w->U[i] + h * P1[i] * w->B0[i];
+    if (c->scheme == 1) {
+        /* exponential Euler (Sec. 3.3): the first stage is the step */
+        memcpy(w->U, Us, sizeof(cplx) * N);
+        return;
+    }
     to_physical(Us, w->u, w->W, ny, nt);
     if (ustar) memcpy(ustar, w->u, sizeof(double) * N);
 
     /* STEP 3: b(x_{n+1}, u*) */
     eval_b(c, xn1, c->nl[s + 1], w->u, w->b);
-    b_spectral(w->b, w->B1, ny, nt);
+    b_spectral(c, w->b, w->B1);
 
     /* STEP 4: F(u^{n+1}) = E F(u^n) + h ((Phi1 - Phi2) F(b^n) + Phi2 F(b*)) */
     for (size_t i = 0; i < N; ++i)
         w->U[i] = E[i] * w->U[i] + h * ((P1[i] - P2[i]) * w->B0[i] + P2[i] * w->B1[i]);
 }
+
+/* Wall time of the step loop of the last orc_run (seconds), without the
+   transforms at its ends; read by the CPU-baseline measurement. */
+static double last_step_seconds = 0.0;
+
+double orc_last_step_seconds(void) { return last_step_seconds; }
 
 int orc_run(const orc_cfg *c, double *u, int first, int n_steps)
 {
@@ -494,7 +638,9 @@ int orc_run(const orc_cfg *c, double *u, int first, int n_steps)
     work w;
     if (work_alloc(c, &w)) { work_free(&w); return -2; }
     to_spectral(u, w.U, c->ny, c->nt);
+    double t0 = omp_get_wtime();
     for (int s = first; s < first + n_steps; ++s) step(c, &w, s, NULL, NULL);
+    last_step_seconds = omp_get_wtime() - t0;
     to_physical(w.U, u, w.W, c->ny, c->nt);
     work_free(&w);
     return 0;
@@ -555,6 +701,7 @@ int orc_adjoint(const orc_cfg *c, const double *u0, double *lam, int first,
                 int n_steps, int ckpt)
 {
     if (first < 0 || first + n_steps > c->nsteps_max || ckpt < 1) return -1;
+    if (c->scheme != 0 || c->reg_eps > 0 || c->vel) return -3;   /* ExpRK22, mean mode zeroed, Burgers b */
     size_t N = (size_t)c->nt * c->ny;
     int nseg = (n_steps + ckpt - 1) / ckpt;
     double *cp = (double *)malloc(sizeof(double) * N * (size_t)nseg);

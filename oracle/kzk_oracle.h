@@ -42,6 +42,24 @@ typedef struct {
     /* Optional prescribed right-hand side used instead of WENO Burgers:
        b(x, u) = force0 + x * force1 (both [ny][nt]); NULL for the normal method. */
     const double *force0, *force1;
+    int    scheme;          /* 0: ExpRK22 (Sec. 3.3 eq. (19)); 1: exponential Euler (Sec. 3.3)  */
+    /* Transport by the velocity field U = (U_par, U_perp)(x, y) of Sec. 2 (b of Sec. 3.3 eq. (16),
+       conservative form of Sec. 3.4 eq. (21)-(22)):
+         b = -d_tau(nl u^2/2 - 2 pi U_par u) - d_y(U_perp u) + (d_y U_perp) u.
+       vel = 0: no transport (b is the Burgers term only);
+       vel = 1: the random field of Algorithm 1 with vel_modes modes, phases vel_phi[n] and
+                angles vel_theta[n] (uniform in [0, 2 pi)), r = vel_lambda (x, y), length scale
+                L = 4 vel_lambda, K_n equispaced in [0.1/L, 9/L], |U~(K_n)| = sqrt(E(K_n)/N),
+                E(K) = sigma_u^2 K^3 L^4 exp(-(K L/2)^2) / 8, normalised by vel_c0;
+       vel = 2: x-independent profiles vel_prof[0..2][ny] = U_par, U_perp, d_y U_perp at y_j. */
+    int    vel;
+    int    vel_modes;
+    const double *vel_phi, *vel_theta;
+    double vel_lambda, vel_sigma_u, vel_c0;
+    const double *vel_prof;
+    double reg_eps;         /* 0: mean tau-mode zeroed (l = 0 there, F(b)(0, .) := 0);
+                               > 0: regularised multiplier of Sec. 3.4, 1/(i kt) replaced by
+                               1/(i kt + reg_eps/(4 pi)) at every tau-mode, F(b) kept whole    */
 } orc_cfg;
 
 /* In-place radix-2 complex FFT of length n (power of two) with unit stride.
@@ -57,7 +75,9 @@ void orc_phi(int k, double zr, double zi, double *out_r, double *out_i);
 
 /* Linear symbol l(m, n) of L at tau-index m, y-index n (Sec. 3.4, z_jk/h):
    l = i * Dbar * ky^2 / (2 kt) - A kt^2, with l = 0 at m = 0 and the
-   diffraction part dropped at the tau-Nyquist m = nt/2. */
+   diffraction part dropped at the tau-Nyquist m = nt/2; with reg_eps > 0,
+   l = -(Dbar/2) ky^2 / (i kt + reg_eps/(4 pi)) - A kt^2 at every m but the
+   tau-Nyquist. */
 void orc_symbol(const orc_cfg *c, int m, int n, double Dbar, double *lr, double *li);
 
 /* WENO5-JS / Lax-Friedrichs discretisation of b = -nl d_tau(u^2/2) on one
@@ -71,13 +91,26 @@ void orc_weno_b(const double *u, int n, double dtau, double nl, double alpha,
 void orc_weno_b_adj(const double *u, int n, double dtau, double nl, double alpha,
                     double eps, const double *g, double *u_bar, double *alpha_bar);
 
+/* Velocity field at (x, y): out = (U_par, U_perp, d_y U_perp) (cfg.vel = 1 or 2). */
+void orc_velocity(const orc_cfg *c, double x, double y, double out[3]);
+
+/* b(x, u) on the whole field [ny][nt] with the Burgers coefficient nl (the
+   same b the stepper uses: WENO5/LF Burgers term, plus the transport terms when
+   cfg.vel != 0). */
+void orc_eval_b(const orc_cfg *c, double x, double nl, const double *u, double *b);
+
 /* Advance the physical field u [ny][nt] by n_steps ExpRK22 steps starting at
    step index first (x_n = x0 + n h).  Returns 0 on success. */
 int orc_run(const orc_cfg *c, double *u, int first, int n_steps);
 
+/* Wall time in seconds of the step loop of the most recent orc_run call
+   (the initial and final transforms excluded). */
+double orc_last_step_seconds(void);
+
 /* Discrete adjoint of orc_run: given u0 (the field at step `first`) and
    lam = dL/du at step first + n_steps, overwrite lam with dL/du0.
-   Checkpoints every ckpt steps, recomputing each segment forward. */
+   Checkpoints every ckpt steps, recomputing each segment forward.
+   ExpRK22 with the mean mode zeroed only (returns -3 otherwise). */
 int orc_adjoint(const orc_cfg *c, const double *u0, double *lam, int first,
                 int n_steps, int ckpt);
 

@@ -41,6 +41,8 @@ class _Cfg(ctypes.Structure):
         ("nsteps_max", ctypes.c_int),
         ("force0", ctypes.POINTER(ctypes.c_double)),
         ("force1", ctypes.POINTER(ctypes.c_double)),
+        ("scheme", ctypes.c_int),
+        ("reg_eps", ctypes.c_double),
     ]
 
 
@@ -82,6 +84,8 @@ def _load(path: str):
     L.orc_run.restype = ctypes.c_int
     L.orc_adjoint.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_adjoint.restype = ctypes.c_int
+    L.orc_last_step_seconds.argtypes = []
+    L.orc_last_step_seconds.restype = ctypes.c_double
     return L
 
 
@@ -128,7 +132,8 @@ class Cfg:
                       int(p.lf_scope if lf_global is None else lf_global),
                       _dp(self.Dbar), _dp(self.nl), ns,
                       null if self.f0 is None else _dp(self.f0),
-                      null if self.f1 is None else _dp(self.f1))
+                      null if self.f1 is None else _dp(self.f1),
+                      int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)))
 
 
 def symbol(p, m: int, n: int, Dbar: float) -> complex:
@@ -163,6 +168,11 @@ def run(p, n_steps=None, first=0, u=None, lf_global=None, force0=None, force1=No
     if rc != 0:
         raise RuntimeError("orc_run failed: %d" % rc)
     return a
+
+
+def last_step_seconds() -> float:
+    """Wall time of the step loop of the last run() (transforms excluded)."""
+    return float(lib().orc_last_step_seconds())
 
 
 def adjoint(p, lam_end: np.ndarray, n_steps=None, ckpt=50, u0=None, first=0, lf_global=None) -> np.ndarray:

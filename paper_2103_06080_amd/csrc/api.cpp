@@ -6,8 +6,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -44,14 +47,18 @@ struct kzk_plan {
     int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
     int y_full = 0;                       // every instance has W n_y = 16 y_threads and n_y >= 512 (full y tiles)
     bool any_D_sched = false;
+    int scheme = 0;                       // 0: ExpRK22, 1: exponential Euler (every solve)
+    bool any_reg = false;                 // some solve uses the regularised multiplier
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
     void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dU = nullptr, *dTab = nullptr, *dTw = nullptr;
     void* dSig = nullptr;                 // flux-difference symbols, sum of M over the solves
     InstDesc* dDesc = nullptr;
-    TauItem* dTau = nullptr;    // tau-pass work list (TAU_THREADS * 16 / M lines per item)
+    TauItem* dTau = nullptr;    // tau-pass work list (tau_threads * 16 / M lines per item)
+    TauItem* dTauAdj = nullptr; // adjoint tau-pass work list (TAU_THREADS * 16 / M lines per item)
     YItem* dY = nullptr;
-    int n_tau_items = 0, n_y_items = 0, max_tau_items = 0;
+    int n_tau_items = 0, n_tau_adj_items = 0, n_y_items = 0, max_tau_items = 0;
+    int tau_threads = kzk::TAU_THREADS;   // tau-pass block size
     void* dTwSt = nullptr;      // per-stage Stockham twiddles
     unsigned* dStatus = nullptr;
     double* dSched = nullptr;
@@ -101,6 +108,17 @@ kzk_status dev_alloc(kzk_plan* p, void** out, size_t bytes) {
     return KZK_OK;
 }
 
+// Free one buffer of dev_alloc (the plan's stream must have finished with it).
+void dev_free(kzk_plan* p, void*& q) {
+    if (!q) return;
+    auto it = std::find(p->owned.begin(), p->owned.end(), q);
+    if (it != p->owned.end()) {
+        p->owned.erase(it);
+        (void)hipFree(q);
+    }
+    q = nullptr;
+}
+
 void drop_graph(kzk_plan* p) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -146,6 +164,8 @@ kzk_status check_params(const kzk_params& q) {
     if (q.lf_scope != 0) return KZK_ERR_ARG;
     if (q.cfl_max < 0) return KZK_ERR_ARG;
     if ((q.D_step || q.nl_node) && q.n_steps_max < 0) return KZK_ERR_ARG;
+    if (q.scheme != 0 && q.scheme != 1) return KZK_ERR_ARG;
+    if (!(q.reg_eps >= 0) || !std::isfinite(q.reg_eps)) return KZK_ERR_ARG;
     return KZK_OK;
 }
 
@@ -170,21 +190,32 @@ int default_y_threads(const kzk_plan* p) {
     return last;
 }
 
-// Descriptors, work lists and tables for the current y-pass block size.
+// Default tau-pass block size: 256 threads (two blocks of 64 KB per compute
+// unit in FP32, whose load, transform and store phases interleave); the
+// autotuner also tries TAU_THREADS_WIDE in FP32.
+int default_tau_threads(const kzk_plan*) { return kzk::TAU_THREADS; }
+
+// Descriptors, work lists and tables for the current y-pass and tau-pass
+// block sizes.
 kzk_status layout(kzk_plan* p) {
-    std::vector<TauItem> tau;
+    std::vector<TauItem> tau, tau_adj;
     std::vector<YItem> ys;
     for (int i = 0; i < p->n_inst; ++i) {
         InstDesc& d = p->desc[i];
         int W = std::min(p->y_threads * 16 / d.n_y, d.M);
         d.W = W;
         d.log2W = ilog2i(W);
+        d.rows_per_tau_block = p->tau_threads * 16 / d.M;
+        const int rows_adj = kzk::TAU_THREADS * 16 / d.M;
         for (int r = 0; r < d.n_y; r += d.rows_per_tau_block) tau.push_back({i, r});
+        for (int r = 0; r < d.n_y; r += rows_adj) tau_adj.push_back({i, r});
         for (int m = 0; m < d.M; m += W) ys.push_back({i, m});
     }
-    // the item arrays are sized for the largest case at create (W >= 1)
-    if ((int)tau.size() > p->max_tau_items) return KZK_ERR_STATE;
+    // the item arrays are sized for the largest case at create (W >= 1,
+    // TAU_THREADS-thread tau blocks)
+    if ((int)tau.size() > p->max_tau_items || (int)tau_adj.size() > p->max_tau_items) return KZK_ERR_STATE;
     p->n_tau_items = (int)tau.size();
+    p->n_tau_adj_items = (int)tau_adj.size();
     p->n_y_items = (int)ys.size();
     p->tau_prog = 1;
     for (const InstDesc& d : p->desc)
@@ -196,6 +227,7 @@ kzk_status layout(kzk_plan* p) {
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dTau, tau.data(), sizeof(TauItem) * tau.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->dTauAdj, tau_adj.data(), sizeof(TauItem) * tau_adj.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dY, ys.data(), sizeof(YItem) * ys.size(), hipMemcpyHostToDevice) != hipSuccess)
         return KZK_ERR_DEVICE;
     return KZK_OK;
@@ -223,12 +255,12 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
                int tiled = 1) {
     ProfScope ps(p, mode == 2 ? KZK_KIND_TAU : KZK_KIND_TRANSFORM);
     if (p->dtype == KZK_F32)
-        return kzk::launch_tau<float>(mode, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in, (float*)u_out,
-                                      Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->tau_prog, p->dStatus,
-                                      p->stream);
-    return kzk::launch_tau<double>(mode, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in, (double*)u_out,
-                                   Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled, p->tau_prog, p->dStatus,
-                                   p->stream);
+        return kzk::launch_tau<float>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in,
+                                      (float*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
+                                      p->tau_prog, p->dStatus, p->stream);
+    return kzk::launch_tau<double>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in,
+                                   (double*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
+                                   p->tau_prog, p->dStatus, p->stream);
 }
 
 // step: the ExpRK22 step, for instances with a D schedule (the y-pass
@@ -242,12 +274,31 @@ hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
                                  p->dB, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
+// The mean tau-mode column of the solves with the regularised multiplier,
+// after y-pass stage 1 of step s.
+hipError_t dc_column(kzk_plan* p, int step) {
+    if (!p->any_reg) return hipSuccess;
+    ProfScope ps(p, KZK_KIND_Y1);
+    if (p->dtype == KZK_F32)
+        return kzk::launch_dc<float>(p->dDesc, p->n_inst, p->dC, p->dP, p->dU, p->dTwSt, step, p->stream);
+    return kzk::launch_dc<double>(p->dDesc, p->n_inst, p->dC, p->dP, p->dU, p->dTwSt, step, p->stream);
+}
+
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
+// ExpRK22 (Algorithm 2): tau-pass at x_n, y-pass stage 1, tau-pass at x_{n+1},
+// y-pass stage 2.  Exponential Euler: its step is the first stage, U* = E U +
+// h Phi1 B, which y-pass stage 1 leaves as C~*; the state U is its y-transform
+// (y-pass stage 0).
 kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
     for (int s = first; s < first + n; ++s) {
         p->prof_now = s % p->prof_every == 0;
         if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
         if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if (dc_column(p, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if (p->scheme == 1) {
+            if (ypass(p, 0) != hipSuccess) return KZK_ERR_DEVICE;
+            continue;
+        }
         if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s + 1) != hipSuccess) return KZK_ERR_DEVICE;
         if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
     }
@@ -258,10 +309,12 @@ kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
 hipError_t tau_adj(kzk_plan* p, int stage, const void* Tin, const void* Rin, const void* ustore, void* out, int node) {
     ProfScope ps(p, KZK_KIND_ADJ_TAU);
     if (p->dtype == KZK_F32)
-        return kzk::launch_tau_adj<float>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const float*)ustore, out,
-                                          p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus, p->stream);
-    return kzk::launch_tau_adj<double>(stage, p->dDesc, p->dTau, p->n_tau_items, Tin, Rin, (const double*)ustore, out,
-                                       p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus, p->stream);
+        return kzk::launch_tau_adj<float>(stage, p->dDesc, p->dTauAdj, p->n_tau_adj_items, Tin, Rin,
+                                          (const float*)ustore, out, p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus,
+                                          p->stream);
+    return kzk::launch_tau_adj<double>(stage, p->dDesc, p->dTauAdj, p->n_tau_adj_items, Tin, Rin,
+                                       (const double*)ustore, out, p->dTw, p->dTwSt, p->log2_ntw, node, p->dStatus,
+                                       p->stream);
 }
 
 hipError_t y_adj(kzk_plan* p, int stage, const void* In, void* Lh, void* Tout, void* Rout) {
@@ -335,10 +388,11 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
     for (int i = 0; i < n_inst; ++i) {
         kzk_status st = check_params(params[i]);
         if (st != KZK_OK) return st;
-        if (params[i].dtype != params[0].dtype) return KZK_ERR_ARG;
+        if (params[i].dtype != params[0].dtype || params[i].scheme != params[0].scheme) return KZK_ERR_ARG;
     }
     kzk_plan* p = new (std::nothrow) kzk_plan();
     if (!p) return KZK_ERR_OOM;
+    p->scheme = params[0].scheme;
     p->arena = arena;
     p->arena_cap = arena ? arena_cap : 0;
     p->n_inst = n_inst;
@@ -362,7 +416,6 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         d.n_y = q.n_y;
         d.M = q.n_tau / 2;
         d.Nh = q.n_y / 2 + 1;
-        d.rows_per_tau_block = kzk::TAU_THREADS * 16 / d.M;
         d.off_state = (long long)so;
         d.off_u = (long long)uo;
         d.off_tab = (long long)to;
@@ -376,12 +429,16 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         d.D_const = q.D;
         d.nl_const = q.nl;
         d.cfl_max = q.cfl_max > 0 ? q.cfl_max : 1.0;
+        d.scheme = q.scheme;
+        d.reg_eps = q.reg_eps;
+        if (q.reg_eps > 0) p->any_reg = true;
         p->u_off[i] = uo;
         so += (size_t)d.M * q.n_y;
         uo += (size_t)q.n_tau * q.n_y;
         to += (size_t)d.M * d.Nh;
         ntw = std::max(ntw, std::max(q.n_tau, q.n_y));
-        max_tau_items += (q.n_y + d.rows_per_tau_block - 1) / d.rows_per_tau_block;
+        const int rows256 = kzk::TAU_THREADS * 16 / d.M;
+        max_tau_items += (q.n_y + rows256 - 1) / rows256;
         max_y_items += d.M;   // W >= 1
         if (q.D_step) {
             p->Dsched[i].assign(q.D_step, q.D_step + q.n_steps_max);
@@ -409,6 +466,7 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         (st = dev_alloc(p, &p->dTw, (size_t)ntw * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dDesc, sizeof(InstDesc) * n_inst)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dTau, sizeof(TauItem) * max_tau_items)) != KZK_OK ||
+        (st = dev_alloc(p, (void**)&p->dTauAdj, sizeof(TauItem) * max_tau_items)) != KZK_OK ||
         (st = dev_alloc(p, &p->dTwSt, (size_t)kzk::stage_twiddle_entries() * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dY, sizeof(YItem) * max_y_items)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dStatus, 256)) != KZK_OK ||
@@ -498,6 +556,7 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
     }
     if (hipMemset(p->dStatus, 0, 256) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     p->y_threads = default_y_threads(p);
+    p->tau_threads = default_tau_threads(p);
     if ((st = layout(p)) != KZK_OK || (st = build_tables(p, 0, false)) != KZK_OK) {
         kzk_destroy(p);
         return st;
@@ -529,6 +588,20 @@ kzk_status kzk_set_graph(kzk_plan* p, int32_t enable) {
 }
 
 int32_t kzk_get_y_threads(const kzk_plan* p) { return p ? p->y_threads : 0; }
+
+int32_t kzk_get_tau_threads(const kzk_plan* p) { return p ? p->tau_threads : 0; }
+
+kzk_status kzk_set_tau_threads(kzk_plan* p, int32_t threads) {
+    if (!p) return KZK_ERR_ARG;
+    if (threads == 0) threads = default_tau_threads(p);
+    if (!kzk::tau_threads_supported(p->dtype == KZK_F64, threads)) return KZK_ERR_ARG;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    drop_graph(p);
+    p->tau_threads = threads;
+    kzk_status st = layout(p);
+    if (st != KZK_OK) return st;
+    return hipStreamSynchronize(p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
 
 
 kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
@@ -677,13 +750,22 @@ kzk_status adjoint_workspace(kzk_plan* p, size_t ckpt, size_t nseg) {
             (st = dev_alloc(p, &p->dR, sb)) != KZK_OK)
             return st;
     }
+    // a larger request replaces the old buffers (freed once the stream is idle)
+    if (ckpt > p->adj_ckpt_cap || nseg > p->adj_seg_cap) {
+        if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    }
     if (ckpt > p->adj_ckpt_cap) {
+        dev_free(p, p->dUn);
+        dev_free(p, p->dUs);
+        p->adj_ckpt_cap = 0;
         kzk_status st;
         if ((st = dev_alloc(p, &p->dUn, ckpt * ub)) != KZK_OK || (st = dev_alloc(p, &p->dUs, ckpt * ub)) != KZK_OK)
             return st;
         p->adj_ckpt_cap = ckpt;
     }
     if (nseg > p->adj_seg_cap) {
+        dev_free(p, p->dCk);
+        p->adj_seg_cap = 0;
         kzk_status st = dev_alloc(p, &p->dCk, 2 * nseg * sb);
         if (st != KZK_OK) return st;
         p->adj_seg_cap = nseg;
@@ -693,45 +775,110 @@ kzk_status adjoint_workspace(kzk_plan* p, size_t ckpt, size_t nseg) {
 
 }  // namespace
 
+namespace {
+
+// Key of a plan in the tuning cache: device architecture, dtype, scheme and
+// every solve's grid (and whether its multipliers are evaluated per step).
+std::string tune_key(const kzk_plan* p) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = "kzk1|" + arch + (p->dtype == KZK_F32 ? "|f32|" : "|f64|") + std::to_string(p->scheme);
+    for (const InstDesc& d : p->desc)
+        k += "|" + std::to_string(d.n_tau) + "x" + std::to_string(d.n_y) + (d.D_step ? "s" : "") +
+             (d.reg_eps > 0 ? "r" : "");
+    return k;
+}
+
+// Look the key up in the cache file: the last line "<key> <y_threads> <tau_threads> <ms>" wins.
+bool tune_lookup(const char* path, const std::string& key, int* yt, int* tt) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    std::vector<char> line(1 << 16);
+    while (std::fgets(line.data(), (int)line.size(), f)) {
+        const char* sp = std::strchr(line.data(), ' ');
+        if (!sp || (size_t)(sp - line.data()) != key.size() || std::strncmp(line.data(), key.c_str(), key.size()))
+            continue;
+        int a = 0, b = 0;
+        if (std::sscanf(sp + 1, "%d %d", &a, &b) == 2) {
+            *yt = a;
+            *tt = b;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const char* path, const std::string& key, int yt, int tt, float ms) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.4f\n", key.c_str(), yt, tt, (double)ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
 extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
     if (!p || !u || n_trial < 1) return -(int32_t)KZK_ERR_ARG;
     if (p->steps_limit >= 0 && n_trial > p->steps_limit) n_trial = (int32_t)p->steps_limit;
     if (n_trial < 1) return -(int32_t)KZK_ERR_STATE;
-    const int cands[3] = {1024, 512, 256};
-    int best = p->y_threads;
+    const char* cache = std::getenv("KZK_TUNE_CACHE");
+    const std::string key = tune_key(p);
+    kzk_status st = KZK_OK;
+    if (cache && *cache) {
+        int yt = 0, tt = 0;
+        if (tune_lookup(cache, key, &yt, &tt) && kzk::y_threads_supported(p->dtype == KZK_F64, yt) &&
+            kzk::tau_threads_supported(p->dtype == KZK_F64, tt)) {
+            if ((st = kzk_set_y_threads(p, yt)) != KZK_OK || (st = kzk_set_tau_threads(p, tt)) != KZK_OK)
+                return -(int32_t)st;
+            return yt;
+        }
+    }
+    const int ycands[3] = {1024, 512, 256};
+    const int tcands[2] = {kzk::TAU_THREADS_WIDE, kzk::TAU_THREADS};
+    int best_y = p->y_threads, best_t = p->tau_threads;
     float best_ms = 1e30f;
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -(int32_t)KZK_ERR_DEVICE;
     const bool prof = p->prof;
     p->prof = false;
-    kzk_status st = KZK_OK;
-    for (int c : cands) {
+    for (int c : ycands) {
         if (!kzk::y_threads_supported(p->dtype == KZK_F64, c)) continue;
         if ((st = kzk_set_y_threads(p, c)) != KZK_OK) break;
-        // one untimed step to warm up, then n_trial timed steps, on the plan's own state
-        if ((st = enqueue_forward(p, u)) != KZK_OK) break;
-        if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
-        if ((st = enqueue_forward(p, u)) != KZK_OK) break;
-        (void)hipEventRecord(a, p->stream);
-        if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
-        (void)hipEventRecord(b, p->stream);
-        if (hipEventSynchronize(b) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (ms < best_ms) { best_ms = ms; best = c; }
+        for (int t : tcands) {
+            if (!kzk::tau_threads_supported(p->dtype == KZK_F64, t)) continue;
+            if ((st = kzk_set_tau_threads(p, t)) != KZK_OK) break;
+            // one untimed step to warm up, then n_trial timed steps, on the plan's own state
+            if ((st = enqueue_forward(p, u)) != KZK_OK) break;
+            if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
+            if ((st = enqueue_forward(p, u)) != KZK_OK) break;
+            (void)hipEventRecord(a, p->stream);
+            if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
+            (void)hipEventRecord(b, p->stream);
+            if (hipEventSynchronize(b) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (ms < best_ms) { best_ms = ms; best_y = c; best_t = t; }
+        }
+        if (st != KZK_OK) break;
     }
     p->prof = prof;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipMemset(p->dStatus, 0, sizeof(unsigned));   // trial steps ran on scratch state
     if (st != KZK_OK) return -(int32_t)st;
-    if ((st = kzk_set_y_threads(p, best)) != KZK_OK) return -(int32_t)st;
-    return best;
+    if ((st = kzk_set_y_threads(p, best_y)) != KZK_OK || (st = kzk_set_tau_threads(p, best_t)) != KZK_OK)
+        return -(int32_t)st;
+    if (cache && *cache) tune_store(cache, key, best_y, best_t, best_ms / (float)n_trial);
+    return best_y;
 }
 
 extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
+    if (p->scheme != 0 || p->any_reg) return KZK_ERR_ARG;   // the adjoint is of ExpRK22, mean mode zeroed
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

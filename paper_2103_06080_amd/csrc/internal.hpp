@@ -10,17 +10,21 @@ namespace kzk {
 enum : unsigned { ST_CFL = 1u, ST_NONFINITE = 2u };
 
 // A tau-line of n_tau reals is handled as a complex sequence of M = n_tau/2
-// points by M/16 threads; a tau-pass block holds TAU_THREADS*16 complex
-// points, i.e. 8192/n_tau lines.
+// points by M/16 threads; a tau-pass block of nt threads holds nt*16 complex
+// points, i.e. nt*32/n_tau lines: TAU_THREADS (256; FP64, the adjoint and the
+// default) or TAU_THREADS_WIDE (512, FP32 only: two 8192-point lines, so the
+// rows that share the 128-byte lines of the column-tiled spectra are written
+// by fewer blocks, still two blocks per compute unit).
 constexpr int TAU_THREADS = 256;
+constexpr int TAU_THREADS_WIDE = 512;
 
 // One solve of a (possibly batched) plan, as the kernels see it.
 struct InstDesc {
     int n_tau, n_y;        // grid points along tau and y
     int M, Nh;             // M = n_tau/2 complex tau-modes (packed), Nh = n_y/2 + 1
     int W, log2W;          // y-pass tile width (columns per block)
-    int rows_per_tau_block;  // lines per tau-pass block (TAU_THREADS * 16 / M)
-    int pad0;
+    int rows_per_tau_block;  // lines per tau-pass block (threads * 16 / M)
+    int scheme;              // 0: ExpRK22, 1: exponential Euler
     long long off_state;   // complex offset of this solve in the C, B, P arrays
     long long off_u;       // real offset of this solve in the packed physical field
     long long off_tab;     // complex offset in each multiplier table
@@ -28,6 +32,7 @@ struct InstDesc {
     long long tab_stride;  // distance between the E, Phi1 and Phi2 tables (all solves)
     double dtau, h, L_tau, L_y, A, weno_eps;
     double D_const, nl_const, cfl_max;
+    double reg_eps;          // > 0: regularised multiplier, 1/(i kt) -> 1/(i kt + reg_eps/(4 pi))
     const double* nl_node;   // device [n_steps_max+1] or nullptr -> nl_const
     const double* D_step;    // device [n_steps_max]   or nullptr -> D_const
     // device [M] complex (working precision): flux-difference symbol sigma_m
@@ -43,10 +48,12 @@ struct YItem { int inst, m0; };
 // Stockham twiddles of all transform lengths 2^4 .. 2^13 (fft.hpp).
 // prog: every instance has M/16 >= W and M >= 256 (tiled spectra; enables
 // progression indexing in the mode-2 kernel).
+// nt: threads per block (tau_threads_supported).
 template <typename T>
-hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
                       int node, int tiled, int prog, unsigned* status, hipStream_t s);
+bool tau_threads_supported(int dtype_is_f64, int nt);
 
 // y-pass over n_items column tiles with at most max_blocks persistent blocks
 // (0: one block per tile).  step: index into the D schedule of instances
@@ -69,6 +76,13 @@ hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_t
 // elements): the flux difference applied to a tau-pass result.
 template <typename T>
 hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, hipStream_t s);
+
+// Mean tau-mode column of the regularised multiplier, after y-pass stage 1:
+// C~*(0, y) and P(0, y) := F_y^-1 [E_0(ky) F_y U(0, .)] for the instances
+// with reg_eps > 0 (one block per instance; the others return at once).
+template <typename T>
+hipError_t launch_dc(const InstDesc* d_desc, int n_inst, void* C, void* P, const void* U, const void* twst, int step,
+                     hipStream_t s);
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,

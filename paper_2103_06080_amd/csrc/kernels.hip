@@ -414,18 +414,19 @@ __device__ __forceinline__ void r2c_post_prog(const cpx<T>* lds, int base, cpx<T
 // MODE 3: as MODE 2, and also stores the physical line u (for the adjoint).
 // PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width and
 // of 16 in every instance (progression indexing of the pre/post-processing
-// pairs).
-template <typename T, int MODE, bool PROG = false>
-__global__ __launch_bounds__(TAU_THREADS) void tau_kernel(const InstDesc* __restrict__ descs,
-                                                          const TauItem* __restrict__ items,
-                                                          const T* __restrict__ u_in, T* __restrict__ u_out,
-                                                          const cpx<T>* __restrict__ Cin, cpx<T>* __restrict__ Bout,
-                                                          const cpx<T>* __restrict__ tw,
-                                                          const cpx<T>* __restrict__ twst, int log2_ntw, int node,
-                                                          int tiled, unsigned* __restrict__ status) {
-    __shared__ alignas(32) cpx<T> lds[padded(TAU_THREADS * 16)];
-    __shared__ T redT[TAU_THREADS / 64];
-    __shared__ int redI[TAU_THREADS / 64];
+// pairs).  NTT: threads per block; a block holds NTT * 16 complex points, the
+// lines rows0 .. rows0 + NTT * 16 / M - 1.
+template <typename T, int MODE, bool PROG = false, int NTT = TAU_THREADS>
+__global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ descs,
+                                                  const TauItem* __restrict__ items,
+                                                  const T* __restrict__ u_in, T* __restrict__ u_out,
+                                                  const cpx<T>* __restrict__ Cin, cpx<T>* __restrict__ Bout,
+                                                  const cpx<T>* __restrict__ tw,
+                                                  const cpx<T>* __restrict__ twst, int log2_ntw, int node,
+                                                  int tiled, unsigned* __restrict__ status) {
+    __shared__ alignas(32) cpx<T> lds[padded(NTT * 16)];
+    __shared__ T redT[NTT / 64];
+    __shared__ int redI[NTT / 64];
     // consecutive rows on one XCD: with column tiles, rows y..y+W-1 share cache lines
     const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
@@ -587,6 +588,17 @@ __device__ void phis_f64(double zr, double zi, cpx<double>& e, cpx<double>& p1, 
     phis_closed_f64(zr, zi, e, p1, p2);
 }
 
+// z = h l of the regularised multiplier (Sec. 3.4, definition of z_jk):
+// l = -(Dbar/2) ky^2 / (i kt + delta) - A kt^2, delta = eps / (4 pi),
+//   = (Dbar/2) ky^2 (i kt - delta) / (kt^2 + delta^2) - A kt^2.
+__device__ __attribute__((noinline)) void regularised_z(double eps, double A, double Dbar, double h, double kt,
+                                                        double ky, double& zr, double& zi) {
+    const double dl = eps / (4.0 * KZK_PI);
+    const double q = 0.5 * Dbar * ky * ky / (kt * kt + dl * dl);
+    zr = h * (-A * kt * kt - q * dl);
+    zi = h * q * kt;
+}
+
 // Flux-difference symbol of tau-mode m (the table built at create, see
 // InstDesc::sigma): the spectrum of b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau is
 // sigma_m times that of F_{i+1/2}.
@@ -604,9 +616,17 @@ __device__ __forceinline__ void mode_multipliers(const InstDesc& d, int m, int n
     const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
     const double kt = 2.0 * KZK_PI * (double)m / d.L_tau;
     const double ky = 2.0 * KZK_PI * (double)n / d.L_y;
-    // z = h l,  l = i Dbar ky^2 / (2 kt) - A kt^2
+    // z = h l,  l = i Dbar ky^2 / (2 kt) - A kt^2 (the regularised symbol out of
+    // line, so that it adds nothing to the registers of the unrolled per-mode code)
+    double zr, zi;
+    if (d.reg_eps > 0.0) {
+        regularised_z(d.reg_eps, d.A, Dbar, h, kt, ky, zr, zi);
+    } else {
+        zr = -h * d.A * kt * kt;
+        zi = h * Dbar * ky * ky / (2.0 * kt);
+    }
     cpx<double> e, p1, p2;
-    phis_f64(-h * d.A * kt * kt, h * Dbar * ky * ky / (2.0 * kt), e, p1, p2);
+    phis_f64(zr, zi, e, p1, p2);
     const double s = 1.0 / (double)d.n_y;
     E = cpx<T>{(T)(e.x * s), (T)(e.y * s)};
     P1 = cpx<T>{(T)(h * s * p1.x), (T)(h * s * p1.y)};
@@ -623,6 +643,50 @@ __device__ __forceinline__ void nyquist_multipliers(const InstDesc& d, T& E, T& 
     E = (T)e.x;
     P1 = (T)(h * p1.x);
     P2 = (T)(h * p2.x);
+}
+
+// ------------------------------------------------------------------ mean tau-mode (regularised multiplier)
+// With the regularised multiplier the mean tau-mode of wavenumber ky has the
+// real symbol l_0 = -(Dbar/2) ky^2 (4 pi / eps).  Column 0 of the spectral
+// arrays holds the mean mode (.x) and the tau-Nyquist mode (.y) of every row
+// in y-physical form; the y-pass keeps the mean as it is.  After stage 1 this
+// kernel applies E_0 along y to the state's mean column,
+//     C~*(0, .) = P(0, .) = F_y^-1 [ E_0 F_y U(0, .) ],
+// which is the whole stage-1 update of that column: the flux difference of b
+// has no mean (sigma_0 = 0), so the Phi terms vanish there; stage 2 then
+// copies P(0, .) to the state as before (U = P + h Phi2 * 0).  One block per
+// instance; the FFT runs on the n_y/16 first threads.
+template <typename T>
+__global__ __launch_bounds__(256) void dc_kernel(const InstDesc* __restrict__ descs, cpx<T>* __restrict__ C,
+                                                 cpx<T>* __restrict__ P, const cpx<T>* __restrict__ U,
+                                                 const cpx<T>* __restrict__ twst, int step) {
+    __shared__ alignas(32) cpx<T> lds[padded(4096)];
+    const InstDesc& d = descs[blockIdx.x];
+    if (!(d.reg_eps > 0.0)) return;
+    const int Ny = d.n_y, W = d.W, tid = threadIdx.x;
+    const long long o = d.off_state;             // tile 0: element (y, column 0) at y W
+    for (int y = tid; y < Ny; y += blockDim.x) lds[padi(y)] = cpx<T>{U[o + (long long)y * W].x, (T)0};
+    __syncthreads();
+    const bool act = tid < (Ny >> 4);
+    lds_fft<T, -1>(lds, 0, Ny, tid, act, twst);
+    __syncthreads();
+    const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
+    const double dl = d.reg_eps / (4.0 * KZK_PI);
+    for (int n = tid; n < Ny; n += blockDim.x) {
+        const int ns = n <= (Ny >> 1) ? n : Ny - n;
+        const double ky = 2.0 * KZK_PI * (double)ns / d.L_y;
+        // E_0 = exp(h l_0) (0 for the large |z| of a small eps), and 1/n_y of the inverse transform
+        const T e = (T)(exp(-d.h * 0.5 * Dbar * ky * ky / dl) / (double)Ny);
+        lds[padi(n)] = e * lds[padi(n)];
+    }
+    __syncthreads();
+    lds_fft<T, 1>(lds, 0, Ny, tid, act, twst);
+    __syncthreads();
+    for (int y = tid; y < Ny; y += blockDim.x) {
+        const T v = lds[padi(y)].x;
+        C[o + (long long)y * W].x = v;
+        P[o + (long long)y * W].x = v;
+    }
 }
 
 // ------------------------------------------------------------------ y-pass
@@ -1445,31 +1509,48 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T>
-hipError_t launch_tau(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
-                      T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, int prog, unsigned* status, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
-    dim3 g(n_items), b(TAU_THREADS);
+template <typename T, int NTT>
+static hipError_t launch_tau_nt(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+                                T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
+                                int node, int tiled, int prog, unsigned* status, hipStream_t s) {
+    dim3 g(n_items), b(NTT);
     const cpx<T>* ci = static_cast<const cpx<T>*>(Cin);
     cpx<T>* bo = static_cast<cpx<T>*>(Bout);
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((tau_kernel<T, 0>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
-    case 1: hipLaunchKernelGGL((tau_kernel<T, 1>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     case 2:
         if (prog && tiled)
-            hipLaunchKernelGGL((tau_kernel<T, 2, true>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws,
-                               log2_ntw, node, tiled, status);
+            hipLaunchKernelGGL((tau_kernel<T, 2, true, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
+                               ws, log2_ntw, node, tiled, status);
         else
-            hipLaunchKernelGGL((tau_kernel<T, 2>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws,
-                               log2_ntw, node, tiled, status);
+            hipLaunchKernelGGL((tau_kernel<T, 2, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
+                               ws, log2_ntw, node, tiled, status);
         break;
-    case 3: hipLaunchKernelGGL((tau_kernel<T, 3>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 3: hipLaunchKernelGGL((tau_kernel<T, 3, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool tau_threads_supported(int is_f64, int nt) { return nt == TAU_THREADS || (nt == TAU_THREADS_WIDE && !is_f64); }
+
+template <typename T>
+hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+                      T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
+                      int node, int tiled, int prog, unsigned* status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (nt == TAU_THREADS)
+        return launch_tau_nt<T, TAU_THREADS>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, twst,
+                                             log2_ntw, node, tiled, prog, status, s);
+    if constexpr (sizeof(T) == 4) {
+        if (nt == TAU_THREADS_WIDE)
+            return launch_tau_nt<T, TAU_THREADS_WIDE>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw,
+                                                      twst, log2_ntw, node, tiled, prog, status, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int NT, bool FULL>
@@ -1578,6 +1659,16 @@ hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void*
 }
 
 template <typename T>
+hipError_t launch_dc(const InstDesc* d_desc, int n_inst, void* C, void* P, const void* U, const void* twst, int step,
+                     hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dc_kernel<T>), dim3(n_inst), dim3(256), 0, s, d_desc, static_cast<cpx<T>*>(C),
+                       static_cast<cpx<T>*>(P), static_cast<const cpx<T>*>(U), static_cast<const cpx<T>*>(twst),
+                       step);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
                          hipStream_t s) {
     if (per_tile <= 0 || n_tiles <= 0) return hipSuccess;
@@ -1658,12 +1749,13 @@ void stage_twiddles(double* out) {
 }
 
 #define KZK_INSTANTIATE(T)                                                                                          \
-    template hipError_t launch_tau<T>(int, const InstDesc*, const TauItem*, int, const T*, T*, const void*, void*,  \
-                                      const void*, const void*, int, int, int, int, unsigned*, hipStream_t);         \
+    template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
+                                      void*, const void*, const void*, int, int, int, int, unsigned*, hipStream_t);  \
     template hipError_t launch_y<T>(int, int, int, const InstDesc*, const YItem*, int, int, void*, const void*,     \
                                     void*, void*, void*, const void*, int, hipStream_t);                             \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, hipStream_t);                    \
+    template hipError_t launch_dc<T>(const InstDesc*, int, void*, void*, const void*, const void*, int, hipStream_t); \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
                                           hipStream_t);                                                              \

@@ -103,6 +103,8 @@ class Problem:
     lf_scope: int = 0           # 0: LF speed per tau-line, 1: global
     D_const: Optional[float] = None
     nl_const: Optional[float] = None
+    scheme: int = 0             # 0: ExpRK22; 1: exponential Euler
+    reg_eps: float = 0.0        # 0: mean tau-mode zeroed; > 0: regularised multiplier with this epsilon
 
     @property
     def dtau(self) -> float:

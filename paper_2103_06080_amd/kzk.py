@@ -22,7 +22,8 @@ STATUS = {0: "KZK_OK", 1: "KZK_ERR_ARG", 2: "KZK_ERR_SIZE", 3: "KZK_ERR_OOM", 4:
 EXPORTS = ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_inst_offset", "kzk_set_stream",
            "kzk_set_graph", "kzk_set_y_threads", "kzk_get_y_threads", "kzk_destroy", "kzk_status_str",
            "kzk_eval_b", "kzk_tau_forward", "kzk_tau_inverse", "kzk_profile_enable", "kzk_profile_read",
-           "kzk_read_tables", "kzk_autotune", "kzk_step_noalloc"]
+           "kzk_read_tables", "kzk_autotune", "kzk_step_noalloc", "kzk_set_tau_threads",
+           "kzk_get_tau_threads"]
 KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "other"]
 
 
@@ -46,6 +47,8 @@ class Params(ctypes.Structure):
         ("lf_scope", ctypes.c_int32),
         ("weno_eps", ctypes.c_double),
         ("cfl_max", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
+        ("reg_eps", ctypes.c_double),
     ]
 
 
@@ -84,6 +87,9 @@ def lib():
         L.kzk_autotune.argtypes = [vp, vp, i32]
         L.kzk_autotune.restype = i32
         L.kzk_step_noalloc.argtypes = [ctypes.POINTER(Params), i32, vp, vp, i32, i32]
+        L.kzk_set_tau_threads.argtypes = [vp, i32]
+        L.kzk_get_tau_threads.argtypes = [vp]
+        L.kzk_get_tau_threads.restype = i32
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -121,7 +127,8 @@ def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None
     return Params(p.n_tau, p.n_y, p.tau0, p.L_tau, p.y0, p.L_y, p.x0, p.h, dtype,
                   float(p.D_const if p.D_const is not None else 0.0), p.A,
                   float(p.nl_const if p.nl_const is not None else 0.0),
-                  D_ptr, nl_ptr, nmax, p.lf_scope, p.weno_eps, cfl_max)
+                  D_ptr, nl_ptr, nmax, p.lf_scope, p.weno_eps, cfl_max,
+                  int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)))
 
 
 def step_noalloc(problems, u, first: int = 0, n_steps: int = 1, dtype: str = "f64", stream=None,
@@ -142,7 +149,7 @@ class Plan:
     """A kzk_plan for one or several solves (uneven grids allowed)."""
 
     def __init__(self, problems, dtype: str = "f64", stream=None, cfl_max: float = 1.0,
-                 y_threads: Optional[int] = None, graph: bool = False):
+                 y_threads: Optional[int] = None, graph: bool = False, tau_threads: Optional[int] = None):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -159,6 +166,8 @@ class Plan:
         self.offsets = [lib().kzk_inst_offset(self.h, i) for i in range(self.n_inst + 1)]
         if y_threads:
             self.set_y_threads(y_threads)
+        if tau_threads:
+            self.set_tau_threads(tau_threads)
         if graph:
             self.set_graph(True)
 
@@ -186,6 +195,17 @@ class Plan:
     @property
     def y_threads(self) -> int:
         return lib().kzk_get_y_threads(self.h)
+
+    def set_tau_threads(self, n: int):
+        _check(lib().kzk_set_tau_threads(self.h, int(n)), "kzk_set_tau_threads")
+
+    @property
+    def tau_threads(self) -> int:
+        return lib().kzk_get_tau_threads(self.h)
+
+    def tuning(self) -> dict:
+        """The block sizes the plan runs with (y-pass and tau-pass)."""
+        return {"y_threads": self.y_threads, "tau_threads": self.tau_threads}
 
 
     # -- buffers

@@ -1,0 +1,151 @@
+"""Parity of the benchmarked 2D path with the FP64 oracle, element by element.
+
+* The 8192 x 4096 inhomogeneous-medium workload exactly as the benchmark
+  runs it (its seeded y-dependent N-wave, nl(x) at the stage nodes, the
+  step average of D(x), absorption; FP32 with 1024-thread full-tile y-passes
+  that evaluate the step's multipliers themselves), for its first steps,
+  against the oracle's march of the same steps (Sec. 3.4 eq. (20),
+  Algorithm 2), in FP64 and in FP32 with every y-pass block size.
+* The 4096 x 2048 homogeneous workload for seeds 0, 1, 2.
+* Rough and shocked data: uniform random fields (b of every line and a few
+  steps) and a march that runs past the formation of a shock.
+
+Bars: relative l2 over the field <= 1e-12 (FP64) / 1e-4 (FP32), and the
+largest pointwise error <= the same factor times max|u| of the reference.
+"""
+import numpy as np
+import pytest
+
+from paper_2103_06080_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-4}
+C3_STEPS = 10
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def max_rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def march(p, dtype, n_steps, y_threads=None):
+    from paper_2103_06080_amd import kzk
+    plan = kzk.Plan(p, dtype=dtype, y_threads=y_threads)
+    u = plan.pack([p.u0])
+    plan.step(u, 0, n_steps)
+    assert plan.poll() == 0
+    yt = plan.y_threads
+    got = plan.unpack(u)[0]
+    plan.close()
+    return got, yt
+
+
+@pytest.fixture(scope="module")
+def c3_case(orc):
+    p = I.c3()
+    print("oracle: 8192 x 4096, %d steps ..." % C3_STEPS, flush=True)
+    ref = orc.run(p, n_steps=C3_STEPS)
+    return p, ref
+
+
+@pytest.mark.parametrize("dtype,yt", [("f64", None), ("f32", 256), ("f32", 512), ("f32", 1024)])
+def test_c3_first_steps_match_oracle(torch_cuda, c3_case, dtype, yt):
+    """The benchmarked march (default y-pass block: 1024 threads in FP32,
+    512 in FP64) and the other block sizes, first steps of the workload."""
+    p, ref = c3_case
+    got, used = march(p, dtype, C3_STEPS, yt)
+    e2, emax = rel_l2(got, ref), max_rel(got, ref)
+    print("c3 %s y_threads %d, %d steps: rel l2 %.3e, max err / max|u| %.3e" % (dtype, used, C3_STEPS, e2, emax))
+    assert e2 < TOL[dtype] and emax < TOL[dtype], (e2, emax)
+
+
+def test_c3_y_pass_block_sizes_agree(torch_cuda, c3_case):
+    """FP32 plans with 256-, 512- and 1024-thread y-passes (different tile
+    widths and kernel forms, the same arithmetic per mode) give the same field."""
+    p, ref = c3_case
+    out = {yt: march(p, "f32", C3_STEPS, yt)[0] for yt in (256, 512, 1024)}
+    scale = np.abs(ref).max()
+    for yt in (256, 512):
+        d = float(np.abs(out[yt] - out[1024]).max()) / scale
+        print("y_threads %d vs 1024: max diff / max|u| %.2e (bitwise equal: %s)"
+              % (yt, d, np.array_equal(out[yt], out[1024])))
+        assert d < 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_seeds_first_steps_match_oracle(torch_cuda, orc, seed, dtype):
+    p = I.c2(seed=seed)
+    n = 20
+    ref = orc.run(p, n_steps=n)
+    got, yt = march(p, dtype, n)
+    e2, emax = rel_l2(got, ref), max_rel(got, ref)
+    print("c2 seed %d %s, %d steps: rel l2 %.3e, max err / max|u| %.3e" % (seed, dtype, n, e2, emax))
+    assert e2 < TOL[dtype] and emax < TOL[dtype]
+
+
+def rough(nt, ny, n_steps, h, seed, D=0.05, nl=0.9, A=1e-4):
+    p = I.Problem(name="rough", n_tau=nt, n_y=ny, h=h, n_steps=n_steps,
+                  D_step=np.full(n_steps, D), nl_node=np.full(n_steps + 1, nl),
+                  u0=I.random_field(seed, (ny, nt)), A=A, D_const=D, nl_const=nl)
+    return p
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt,ny", [(256, 16), (4096, 32), (8192, 16)])
+def test_weno_b_of_random_fields_matches_oracle(torch_cuda, orc, dtype, nt, ny):
+    """Uniform random lines: every face is non-smooth, the nonlinear weights
+    are far from the ideal ones and the LF speed comes from a random point."""
+    from paper_2103_06080_amd import kzk
+    p = rough(nt, ny, 1, 1e-4, seed=11 + nt)
+    plan = kzk.Plan(p, dtype=dtype)
+    b = plan.eval_b(plan.pack([p.u0]), 0).double().cpu().numpy().reshape(ny, nt)
+    ref = np.stack([orc.weno_b(p.u0[j], p.dtau, 0.9, 0.9 * np.abs(p.u0[j]).max()) for j in range(ny)])
+    e2, emax = rel_l2(b, ref), max_rel(b, ref)
+    print("random b %s %dx%d: rel l2 %.2e, max %.2e" % (dtype, nt, ny, e2, emax))
+    # FP32: b is a difference of O(1) fluxes over dtau, its rounding relative to max|b| ~ 1e-6
+    bar = 1e-12 if dtype == "f64" else 2e-5
+    assert e2 < bar and emax < bar
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_steps_of_a_random_field_match_oracle(torch_cuda, orc, dtype):
+    p = rough(1024, 512, 5, 2e-4, seed=5)
+    ref = orc.run(p)
+    got, _ = march(p, dtype, p.n_steps)
+    e2, emax = rel_l2(got, ref), max_rel(got, ref)
+    print("random field %s, 5 steps: rel l2 %.2e, max %.2e" % (dtype, e2, emax))
+    assert e2 < TOL[dtype] and emax < TOL[dtype]
+
+
+def shocked(nt, ny, n_steps):
+    """Compressive ramp of half-width T = 0.3 and amplitude 2 with sharp edges:
+    the central shock forms at x = T / a = 0.15, half-way through the march."""
+    p = I.Problem(name="shock", n_tau=nt, n_y=ny, h=1e-3, n_steps=n_steps,
+                  D_step=np.full(n_steps, 0.05), nl_node=np.full(n_steps + 1, 1.0),
+                  u0=np.zeros((ny, nt)), A=0.0, D_const=0.05, nl_const=1.0)
+    p.u0 = I.nwave(p.tau(), p.y(), 0.3, 2.0, 0.02, [(0.05, 1, 0.3), (0.03, 2, 1.0)], p.y0, p.L_y)
+    return p
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_march_through_shock_formation_matches_oracle(torch_cuda, orc, dtype):
+    p = shocked(1024, 128, 300)
+    ref = orc.run(p)
+    # a shock has formed: the largest jump between neighbouring points is most of max|u|
+    assert np.abs(np.diff(ref, axis=1)).max() > 0.5 * np.abs(ref).max()
+    got, _ = march(p, dtype, p.n_steps)
+    e2, emax = rel_l2(got, ref), max_rel(got, ref)
+    print("shock %s, 300 steps: rel l2 %.2e, max %.2e" % (dtype, e2, emax))
+    assert e2 < TOL[dtype] and emax < TOL[dtype]

@@ -12,6 +12,7 @@ import shutil
 import pytest
 
 import test_oracle_pins as P
+import test_oracle_variants as V
 import test_oracle_weno_exact as X
 
 ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
@@ -47,7 +48,7 @@ MUTATIONS = [
      [lambda o: P.test_absorption_mode_decays_exactly(o, 3)]),
     ("diffraction kept at the tau-Nyquist index", "if (2 * m == c->nt) return absorb;", "", None,
      [P.test_symbol_special_columns_and_hermitian_symmetry]),
-    ("mean tau-mode of F(b) kept", "for (int n = 0; n < ny; ++n) B[(size_t)n * nt] = 0;", "", None,
+    ("mean tau-mode of F(b) kept", "for (int n = 0; n < c->ny; ++n) B[(size_t)n * c->nt] = 0;", "", None,
      [P.test_mean_tau_mode_of_b_is_zeroed]),
     ("stage values transposed in the combine",
      "h * ((P1[i] - P2[i]) * w->B0[i] + P2[i] * w->B1[i])", "h * ((P1[i] - P2[i]) * w->B1[i] + P2[i] * w->B0[i])",
@@ -70,6 +71,18 @@ MUTATIONS = [
     ("adjoint: weight derivative factor", "double da = -2.0 * d[r] / pow(eps + beta[r], 3) * dbeta[r][s];",
      "double da = -1.0 * d[r] / pow(eps + beta[r], 3) * dbeta[r][s];", None,
      [P.test_weno_adjoint_matches_finite_differences]),
+    ("regularised shift without 1/(4 pi)", "I * kt + c->reg_eps / (4.0 * PI)", "I * kt + c->reg_eps", None,
+     [V.test_regularised_mean_column_follows_its_closed_form]),
+    ("regularised diffraction sign", "return absorb - 0.5 * Dbar * ky * ky / (I * kt",
+     "return absorb + 0.5 * Dbar * ky * ky / (I * kt", None,
+     [V.test_regularised_equals_unregularised_on_fields_of_zero_tau_mean]),
+    ("regularised multiplier zeroes the mean of F(b)", "    if (c->reg_eps > 0) return;\n", "", None,
+     [V.test_regularised_multiplier_keeps_the_mean_of_b]),
+    ("exponential Euler runs the second stage", "if (c->scheme == 1) {", "if (c->scheme == 2) {", None,
+     [V.test_exponential_euler_first_order, V.test_exponential_euler_not_exact_for_x_dependent_forcing]),
+    ("exponential Euler with phi2", "        memcpy(w->U, Us, sizeof(cplx) * N);",
+     "        for (size_t i = 0; i < N; ++i) w->U[i] = E[i] * w->U[i] + h * P2[i] * w->B0[i];", None,
+     [V.test_exponential_euler_exact_for_constant_forcing]),
     ("adjoint: multiplier not conjugated", "w->W[i] = conj(M[i]) * V[i];", "w->W[i] = M[i] * V[i];", None,
      [lambda o: P.test_full_adjoint_matches_central_differences(o, 3)]),
 ]
