@@ -43,6 +43,9 @@ typedef struct {
        b(x, u) = force0 + x * force1 (both [ny][nt]); NULL for the normal method. */
     const double *force0, *force1;
     int    scheme;          /* 0: ExpRK22 (Sec. 3.3 eq. (19)); 1: exponential Euler (Sec. 3.3)  */
+    double reg_eps;         /* 0: mean tau-mode zeroed (l = 0 there, F(b)(0, .) := 0);
+                               > 0: regularised multiplier of Sec. 3.4, 1/(i kt) replaced by
+                               1/(i kt + reg_eps/(4 pi)) at every tau-mode, F(b) kept whole    */
     /* Transport by the velocity field U = (U_par, U_perp)(x, y) of Sec. 2 (b of Sec. 3.3 eq. (16),
        conservative form of Sec. 3.4 eq. (21)-(22)):
          b = -d_tau(nl u^2/2 - 2 pi U_par u) - d_y(U_perp u) + (d_y U_perp) u.
@@ -57,9 +60,6 @@ typedef struct {
     const double *vel_phi, *vel_theta;
     double vel_lambda, vel_sigma_u, vel_c0;
     const double *vel_prof;
-    double reg_eps;         /* 0: mean tau-mode zeroed (l = 0 there, F(b)(0, .) := 0);
-                               > 0: regularised multiplier of Sec. 3.4, 1/(i kt) replaced by
-                               1/(i kt + reg_eps/(4 pi)) at every tau-mode, F(b) kept whole    */
 } orc_cfg;
 
 /* In-place radix-2 complex FFT of length n (power of two) with unit stride.

@@ -43,6 +43,14 @@ class _Cfg(ctypes.Structure):
         ("force1", ctypes.POINTER(ctypes.c_double)),
         ("scheme", ctypes.c_int),
         ("reg_eps", ctypes.c_double),
+        ("vel", ctypes.c_int),
+        ("vel_modes", ctypes.c_int),
+        ("vel_phi", ctypes.POINTER(ctypes.c_double)),
+        ("vel_theta", ctypes.POINTER(ctypes.c_double)),
+        ("vel_lambda", ctypes.c_double),
+        ("vel_sigma_u", ctypes.c_double),
+        ("vel_c0", ctypes.c_double),
+        ("vel_prof", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -84,6 +92,8 @@ def _load(path: str):
     L.orc_run.restype = ctypes.c_int
     L.orc_adjoint.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_adjoint.restype = ctypes.c_int
+    L.orc_velocity.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double, dp]
+    L.orc_eval_b.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double, dp, dp]
     L.orc_last_step_seconds.argtypes = []
     L.orc_last_step_seconds.restype = ctypes.c_double
     return L
@@ -128,12 +138,20 @@ class Cfg:
         self.f0 = None if force0 is None else np.ascontiguousarray(force0, dtype=np.float64)
         self.f1 = None if force1 is None else np.ascontiguousarray(force1, dtype=np.float64)
         null = ctypes.POINTER(ctypes.c_double)()
+        vel = int(getattr(p, "vel", 0))
+        arr = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        self.vphi, self.vtheta = arr(getattr(p, "vel_phi", None)), arr(getattr(p, "vel_theta", None))
+        self.vprof = arr(getattr(p, "vel_prof", None))
+        ptr = lambda a: null if a is None else _dp(a)
         self.c = _Cfg(p.n_tau, p.n_y, p.tau0, p.L_tau, p.y0, p.L_y, p.x0, p.h, p.A, p.weno_eps,
                       int(p.lf_scope if lf_global is None else lf_global),
                       _dp(self.Dbar), _dp(self.nl), ns,
                       null if self.f0 is None else _dp(self.f0),
                       null if self.f1 is None else _dp(self.f1),
-                      int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)))
+                      int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)),
+                      vel, int(getattr(p, "vel_modes", 0)), ptr(self.vphi), ptr(self.vtheta),
+                      float(getattr(p, "vel_lambda", 0.0)), float(getattr(p, "vel_sigma_u", 0.0)),
+                      float(getattr(p, "vel_c0", 1.0)), ptr(self.vprof))
 
 
 def symbol(p, m: int, n: int, Dbar: float) -> complex:
@@ -141,6 +159,23 @@ def symbol(p, m: int, n: int, Dbar: float) -> complex:
     r, i = ctypes.c_double(), ctypes.c_double()
     lib().orc_symbol(ctypes.byref(c.c), m, n, Dbar, ctypes.byref(r), ctypes.byref(i))
     return complex(r.value, i.value)
+
+
+def velocity(p, x: float, y: float) -> np.ndarray:
+    """(U_par, U_perp, d_y U_perp) of the problem's velocity field at (x, y)."""
+    c = Cfg(p, n_steps=0)
+    out = np.zeros(3)
+    lib().orc_velocity(ctypes.byref(c.c), float(x), float(y), _dp(out))
+    return out
+
+
+def eval_b(p, x: float, nl: float, u: np.ndarray) -> np.ndarray:
+    """b(x, u) on the whole field, as the stepper evaluates it."""
+    c = Cfg(p, n_steps=0)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    b = np.empty_like(u)
+    lib().orc_eval_b(ctypes.byref(c.c), float(x), float(nl), _dp(u), _dp(b))
+    return b
 
 
 def weno_b(u: np.ndarray, dtau: float, nl: float, alpha: float, eps: float = 1e-6) -> np.ndarray:

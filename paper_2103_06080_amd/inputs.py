@@ -105,6 +105,17 @@ class Problem:
     nl_const: Optional[float] = None
     scheme: int = 0             # 0: ExpRK22; 1: exponential Euler
     reg_eps: float = 0.0        # 0: mean tau-mode zeroed; > 0: regularised multiplier with this epsilon
+    # transport by a velocity field: vel = 0 none, 1 the random field of Sec. 2
+    # (vel_modes modes with phases vel_phi and angles vel_theta), 2 fixed
+    # profiles vel_prof[3][n_y] (U_par, U_perp, d_y U_perp; oracle tests only)
+    vel: int = 0
+    vel_modes: int = 0
+    vel_phi: Optional[np.ndarray] = None
+    vel_theta: Optional[np.ndarray] = None
+    vel_lambda: float = 6.86    # lambda = T0 c0 (m): T0 = 0.02 s, c0 = 343 m/s
+    vel_sigma_u: float = 3.0    # sigma_u (m/s)
+    vel_c0: float = 343.0       # ambient sound speed (m/s), U is normalised by it
+    vel_prof: Optional[np.ndarray] = None
 
     @property
     def dtau(self) -> float:
@@ -242,6 +253,15 @@ C5_FD_EPS = 1e-6
 C5_N_DIRECTIONS = 32
 C5_KAPPA = 20.0
 C5_WINDOW = (-2.0, 2.0)
+
+
+def medium(seed: int, n_modes: int = 200) -> dict:
+    """Random numbers of the velocity field of Sec. 2: per mode n, in order,
+    the phase phi_n and the angle theta_n, both uniform in [0, 2 pi)
+    (Algorithm 1 draws them as two independent sequences; here they are
+    interleaved draws of one SplitMix64 stream).  Returned as Problem fields."""
+    u = splitmix_uniform_array(seed, 2 * n_modes).reshape(n_modes, 2) * (2 * math.pi)
+    return dict(vel=1, vel_modes=n_modes, vel_phi=u[:, 0].copy(), vel_theta=u[:, 1].copy())
 
 
 def fd_direction(r: int, shape) -> np.ndarray:

@@ -12,6 +12,7 @@ import shutil
 import pytest
 
 import test_oracle_pins as P
+import test_oracle_transport as TR
 import test_oracle_variants as V
 import test_oracle_weno_exact as X
 
@@ -83,6 +84,23 @@ MUTATIONS = [
     ("exponential Euler with phi2", "        memcpy(w->U, Us, sizeof(cplx) * N);",
      "        for (size_t i = 0; i < N; ++i) w->U[i] = E[i] * w->U[i] + h * P2[i] * w->B0[i];", None,
      [V.test_exponential_euler_exact_for_constant_forcing]),
+    ("transport: axial velocity sign", "double cpar = 2.0 * PI * vel[3 * j];", "double cpar = -2.0 * PI * vel[3 * j];",
+     None, [TR.test_constant_axial_velocity_translates_in_tau, TR.test_axial_transport_term_equals_exact_evaluation]),
+    ("transport: LF speed along tau ignores U_par", "alpha = fmax(alpha, fabs(nl * uj[k] - cpar));",
+     "alpha = fmax(alpha, fabs(nl * uj[k]));", None, [TR.test_axial_transport_term_equals_exact_evaluation]),
+    ("transport: LF speed along y from U_par", "ay = fmax(ay, fabs(vel[3 * j + 1]));", "ay = fmax(ay, fabs(vel[3 * j]));",
+     None, [TR.test_transverse_transport_term_equals_exact_evaluation]),
+    ("transport: source sign", "/ dy + vel[3 * j + 2] * u[", "/ dy - vel[3 * j + 2] * u[", None,
+     [TR.test_transport_flux_differences_telescope]),
+    ("transport: y difference over dtau", "b[(size_t)j * nt + k] += -(F[j] - F[wrap(j - 1, ny)]) / dy",
+     "b[(size_t)j * nt + k] += -(F[j] - F[wrap(j - 1, ny)]) / dtau", None,
+     [TR.test_transport_b_converges_at_fifth_order]),
+    ("velocity: atan2 arguments swapped", "double ang = atan2(y, x);", "double ang = atan2(x, y);", None,
+     [TR.test_velocity_equals_cartesian_mode_sum]),
+    ("velocity: amplitude without 1/N", "amp[n] = sqrt(E / (double)N) / c->vel_c0;",
+     "amp[n] = sqrt(E) / c->vel_c0;", None, [TR.test_velocity_field_is_bounded_as_stated]),
+    ("velocity: mode vector not normal to K", "double U1 = -amp[n] * sin(th), U2 = amp[n] * cos(th);",
+     "double U1 = amp[n] * cos(th), U2 = amp[n] * sin(th);", None, [TR.test_velocity_field_is_divergence_free]),
     ("adjoint: multiplier not conjugated", "w->W[i] = conj(M[i]) * V[i];", "w->W[i] = M[i] * V[i];", None,
      [lambda o: P.test_full_adjoint_matches_central_differences(o, 3)]),
 ]
