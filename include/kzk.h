@@ -82,6 +82,23 @@ typedef struct {
                                every tau-mode, so the mean mode of every ky != 0 is damped
                                by exp(-h (D/2) ky^2 4 pi / reg_eps); the paper takes the
                                machine epsilon of the working precision                    */
+    /* Transport by the random velocity field of Sec. 2 (Algorithm 1): b gains the
+       terms 2 pi U_par d_tau u - U_perp d_y u of Sec. 3.3 eq. (16), taken in the
+       conservative form of Sec. 3.4 eq. (21)-(22):
+         b = -d_tau(nl u^2/2 - 2 pi U_par u) - d_y(U_perp u) + (d_y U_perp) u,
+       WENO5/LF along tau (speed max |nl u - 2 pi U_par| per tau-line) and along y
+       (speed max_j |U_perp|), with U evaluated at the stage nodes x_n, x_{n+1}.
+       vel = 0: no transport; vel = 1: the field of vel_modes modes with phases
+       vel_phi[n] and angles vel_theta[n] (host arrays, radians), r = vel_lambda (x, y),
+       length scale L = 4 vel_lambda, |K_n| equispaced in [0.1/L, 9/L],
+       |U~(K_n)| = sqrt(E(|K_n|)/N), E(K) = sigma_u^2 K^3 L^4 exp(-(K L/2)^2) / 8,
+       normalised by vel_c0 (the paper: lambda = 6.86 m, sigma_u = 3 m/s,
+       c0 = 343 m/s).  Needs 1 <= n_steps_max <= 65534 (the field is tabulated
+       at every node); the same vel for every solve of a plan.                    */
+    int32_t vel;
+    int32_t vel_modes;
+    const double *vel_phi, *vel_theta;
+    double vel_lambda, vel_sigma_u, vel_c0;
 } kzk_params;
 
 /* Create a plan for n_inst independent solves (n_inst >= 1), params[i] for
@@ -106,7 +123,8 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * first_step and lam_dev = dL/du at step first_step + n_steps, write dL/du0
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
  * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
- * with the mean mode zeroed (scheme 0, reg_eps 0); KZK_ERR_ARG otherwise. */
+ * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0);
+ * KZK_ERR_ARG otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 
@@ -165,6 +183,7 @@ enum {
     KZK_KIND_TRANSFORM = 4,  /* plain tau-transforms at the ends of a march              */
     KZK_KIND_ADJ_TAU = 5,    /* adjoint tau-pass (WENO5 Jacobian transpose)              */
     KZK_KIND_ADJ_Y = 6,      /* adjoint y-passes                                         */
+    KZK_KIND_TRANSPORT = 7,  /* transverse transport pass (WENO5 along y, source)        */
     KZK_N_KINDS = 8
 };
 

@@ -49,6 +49,13 @@ struct kzk_plan {
     bool any_D_sched = false;
     int scheme = 0;                       // 0: ExpRK22, 1: exponential Euler (every solve)
     bool any_reg = false;                 // some solve uses the regularised multiplier
+    // transport by the random velocity field (every solve or none): the
+    // physical field and transverse part of b per stage, its tau-spectrum,
+    // velocity tables at the nodes, and the work list of the transverse pass
+    bool transport = false;
+    void *dUph = nullptr, *dByp = nullptr, *dBys = nullptr;
+    kzk::YwItem* dYw = nullptr;
+    int n_yw_items = 0;
     long long steps_limit = -1;           // -1: unlimited (constant coefficients)
 
     void *dC = nullptr, *dB = nullptr, *dP = nullptr, *dU = nullptr, *dTab = nullptr, *dTw = nullptr;
@@ -166,6 +173,14 @@ kzk_status check_params(const kzk_params& q) {
     if ((q.D_step || q.nl_node) && q.n_steps_max < 0) return KZK_ERR_ARG;
     if (q.scheme != 0 && q.scheme != 1) return KZK_ERR_ARG;
     if (!(q.reg_eps >= 0) || !std::isfinite(q.reg_eps)) return KZK_ERR_ARG;
+    if (q.vel != 0 && q.vel != 1) return KZK_ERR_ARG;
+    if (q.vel == 1) {
+        if (q.vel_modes < 1 || !q.vel_phi || !q.vel_theta || q.n_steps_max < 1 || q.n_steps_max > 65534)
+            return KZK_ERR_ARG;
+        if (!(q.vel_lambda > 0) || !(q.vel_c0 > 0) || !(q.vel_sigma_u >= 0) || !std::isfinite(q.vel_lambda) ||
+            !std::isfinite(q.vel_c0) || !std::isfinite(q.vel_sigma_u))
+            return KZK_ERR_ARG;
+    }
     return KZK_OK;
 }
 
@@ -194,6 +209,60 @@ int default_y_threads(const kzk_plan* p) {
 // unit in FP32, whose load, transform and store phases interleave); the
 // autotuner also tries TAU_THREADS_WIDE in FP32.
 int default_tau_threads(const kzk_plan*) { return kzk::TAU_THREADS; }
+
+// Transport (vel = 1): the work arrays, the transverse pass's work list and
+// the velocity tables of every solve at the nodes x_n = x0 + n h,
+// n = 0 .. n_steps_max (Algorithm 1, evaluated on the device in FP64 from the
+// per-mode constants built here: K_n lambda with K_n equispaced in
+// [0.1/L, 9/L], L = 4 lambda, and |U~(K_n)| / c0 = sqrt(E(K_n)/N) / c0 with
+// E(K) = sigma_u^2 K^3 L^4 exp(-(K L/2)^2) / 8).
+kzk_status setup_transport(kzk_plan* p, const kzk_params* params) {
+    const size_t ub = p->u_off[p->n_inst] * p->esz;
+    kzk_status st;
+    if ((st = dev_alloc(p, &p->dUph, ub)) != KZK_OK || (st = dev_alloc(p, &p->dByp, ub)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dBys, p->state_elems * 2 * p->esz)) != KZK_OK)
+        return st;
+    std::vector<kzk::YwItem> items;
+    for (int i = 0; i < p->n_inst; ++i)
+        for (int k0 = 0; k0 < p->desc[i].n_tau; k0 += kzk::YW_THREADS)
+            for (int j0 = 0; j0 < p->desc[i].n_y; j0 += kzk::YW_SEG) items.push_back({i, k0, j0});
+    p->n_yw_items = (int)items.size();
+    if ((st = dev_alloc(p, (void**)&p->dYw, sizeof(kzk::YwItem) * items.size())) != KZK_OK) return st;
+    if (hipMemcpy(p->dYw, items.data(), sizeof(kzk::YwItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return KZK_ERR_DEVICE;
+    for (int i = 0; i < p->n_inst; ++i) {
+        const kzk_params& q = params[i];
+        const int N = q.vel_modes, nodes = q.n_steps_max + 1, ny = q.n_y;
+        const double L = 4.0 * q.vel_lambda, kmin = 0.1 / L, kmax = 9.0 / L;
+        std::vector<double> m(5 * (size_t)N);
+        for (int n = 0; n < N; ++n) {
+            const double K = N > 1 ? kmin + (kmax - kmin) * (double)n / (double)(N - 1) : kmin;
+            const double E = 0.125 * q.vel_sigma_u * q.vel_sigma_u * K * K * K * L * L * L * L *
+                             std::exp(-(K * L / 2.0) * (K * L / 2.0));
+            m[n] = K * q.vel_lambda;
+            m[N + n] = std::sqrt(E / (double)N) / q.vel_c0;
+            m[2 * N + n] = std::cos(q.vel_theta[n]);
+            m[3 * N + n] = std::sin(q.vel_theta[n]);
+            m[4 * N + n] = q.vel_phi[n];
+        }
+        void *dm = nullptr, *tab = nullptr, *amax = nullptr;
+        if ((st = dev_alloc(p, &dm, sizeof(double) * m.size())) != KZK_OK ||
+            (st = dev_alloc(p, &tab, sizeof(double) * 3 * (size_t)ny * nodes)) != KZK_OK ||
+            (st = dev_alloc(p, &amax, sizeof(double) * nodes)) != KZK_OK)
+            return st;
+        if (hipMemcpy(dm, m.data(), sizeof(double) * m.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return KZK_ERR_DEVICE;
+        p->desc[i].vel_tab = static_cast<const double*>(tab);
+        p->desc[i].vel_amax = static_cast<const double*>(amax);
+        // the kernels read n_y and y0, dy of instance i from the descriptors
+        if (hipMemcpy(p->dDesc + i, &p->desc[i], sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
+            return KZK_ERR_DEVICE;
+        if (kzk::launch_velocity(p->dDesc, i, static_cast<const double*>(dm), N, q.x0, q.h, nodes,
+                                 static_cast<double*>(tab), static_cast<double*>(amax), p->stream) != hipSuccess)
+            return KZK_ERR_DEVICE;
+    }
+    return hipStreamSynchronize(p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
+}
 
 // Descriptors, work lists and tables for the current y-pass and tau-pass
 // block sizes.
@@ -267,21 +336,49 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
 // computes their multipliers; the others read the tables built at create).
 hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
+    const void* by = stage > 0 && p->transport ? p->dBys : nullptr;
     if (p->dtype == KZK_F32)
         return kzk::launch_y<float>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
-                                    p->dB, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+                                    p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
     return kzk::launch_y<double>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
-                                 p->dB, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+                                 p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
 // The mean tau-mode column of the solves with the regularised multiplier,
-// after y-pass stage 1 of step s.
-hipError_t dc_column(kzk_plan* p, int step) {
-    if (!p->any_reg) return hipSuccess;
-    ProfScope ps(p, KZK_KIND_Y1);
+// after y-pass stage `stage` of step s (stage 2 only with transport).
+hipError_t dc_column(kzk_plan* p, int stage, int step) {
+    if (!p->any_reg || (stage == 2 && !p->transport)) return hipSuccess;
+    ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : KZK_KIND_Y2);
+    const void* by = p->transport ? p->dBys : nullptr;
     if (p->dtype == KZK_F32)
-        return kzk::launch_dc<float>(p->dDesc, p->n_inst, p->dC, p->dP, p->dU, p->dTwSt, step, p->stream);
-    return kzk::launch_dc<double>(p->dDesc, p->n_inst, p->dC, p->dP, p->dU, p->dTwSt, step, p->stream);
+        return kzk::launch_dc<float>(stage, p->dDesc, p->n_inst, p->dC, p->dP, p->dU, by, p->dTwSt, step, p->stream);
+    return kzk::launch_dc<double>(stage, p->dDesc, p->n_inst, p->dC, p->dP, p->dU, by, p->dTwSt, step, p->stream);
+}
+
+// b at node x_node with transport (Sec. 3.4 eq. (21)-(22)): the tau-pass
+// leaves the spectrum of the tau face fluxes (axial and Burgers terms) in dB
+// and the physical field in dUph; the transverse pass writes its part of b
+// (WENO5 of U_perp u along y plus the source) to dByp, whose tau-transform
+// is dBys.  The y-pass then takes sigma_m dB + dBys.
+kzk_status transport_b(kzk_plan* p, int node) {
+    if (tau(p, 3, nullptr, p->dUph, p->dC, p->dB, node) != hipSuccess) return KZK_ERR_DEVICE;
+    {
+        ProfScope ps(p, KZK_KIND_TRANSPORT);
+        hipError_t e = p->dtype == KZK_F32
+            ? kzk::launch_yweno<float>(p->dDesc, p->dYw, p->n_yw_items, (const float*)p->dUph, (float*)p->dByp, node,
+                                       p->dStatus, p->stream)
+            : kzk::launch_yweno<double>(p->dDesc, p->dYw, p->n_yw_items, (const double*)p->dUph, (double*)p->dByp,
+                                        node, p->dStatus, p->stream);
+        if (e != hipSuccess) return KZK_ERR_DEVICE;
+    }
+    if (tau(p, 0, p->dByp, nullptr, nullptr, p->dBys, 0) != hipSuccess) return KZK_ERR_DEVICE;
+    return KZK_OK;
+}
+
+// b at a stage node: the fused tau-pass, or the three passes of transport.
+kzk_status stage_b(kzk_plan* p, int node) {
+    if (p->transport) return transport_b(p, node);
+    return tau(p, 2, nullptr, nullptr, p->dC, p->dB, node) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
 }
 
 // Steps s .. s+n-1 on the spectral state (dU, with dC its tau-spectrum per y-row).
@@ -290,17 +387,19 @@ hipError_t dc_column(kzk_plan* p, int step) {
 // h Phi1 B, which y-pass stage 1 leaves as C~*; the state U is its y-transform
 // (y-pass stage 0).
 kzk_status enqueue_steps(kzk_plan* p, int first, int n) {
+    kzk_status st;
     for (int s = first; s < first + n; ++s) {
         p->prof_now = s % p->prof_every == 0;
-        if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if ((st = stage_b(p, s)) != KZK_OK) return st;
         if (ypass(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
-        if (dc_column(p, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if (dc_column(p, 1, s) != hipSuccess) return KZK_ERR_DEVICE;
         if (p->scheme == 1) {
             if (ypass(p, 0) != hipSuccess) return KZK_ERR_DEVICE;
             continue;
         }
-        if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, s + 1) != hipSuccess) return KZK_ERR_DEVICE;
+        if ((st = stage_b(p, s + 1)) != KZK_OK) return st;
         if (ypass(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
+        if (dc_column(p, 2, s) != hipSuccess) return KZK_ERR_DEVICE;
     }
     p->prof_now = true;
     return KZK_OK;
@@ -388,11 +487,14 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
     for (int i = 0; i < n_inst; ++i) {
         kzk_status st = check_params(params[i]);
         if (st != KZK_OK) return st;
-        if (params[i].dtype != params[0].dtype || params[i].scheme != params[0].scheme) return KZK_ERR_ARG;
+        if (params[i].dtype != params[0].dtype || params[i].scheme != params[0].scheme ||
+            params[i].vel != params[0].vel)
+            return KZK_ERR_ARG;
     }
     kzk_plan* p = new (std::nothrow) kzk_plan();
     if (!p) return KZK_ERR_OOM;
     p->scheme = params[0].scheme;
+    p->transport = params[0].vel == 1;
     p->arena = arena;
     p->arena_cap = arena ? arena_cap : 0;
     p->n_inst = n_inst;
@@ -432,6 +534,9 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         d.scheme = q.scheme;
         d.reg_eps = q.reg_eps;
         if (q.reg_eps > 0) p->any_reg = true;
+        d.vel = q.vel;
+        d.y0 = q.y0;
+        d.dy = q.L_y / q.n_y;
         p->u_off[i] = uo;
         so += (size_t)d.M * q.n_y;
         uo += (size_t)q.n_tau * q.n_y;
@@ -553,6 +658,10 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
             e = hipMemcpy(p->dTwSt, st64.data(), st64.size() * sizeof(double), hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
+    }
+    if (p->transport && (st = setup_transport(p, params)) != KZK_OK) {
+        kzk_destroy(p);
+        return st;
     }
     if (hipMemset(p->dStatus, 0, 256) != hipSuccess) { kzk_destroy(p); return KZK_ERR_DEVICE; }
     p->y_threads = default_y_threads(p);
@@ -693,12 +802,15 @@ kzk_status kzk_eval_b(kzk_plan* p, const void* u, int32_t node, void* b) {
     if (!p || !u || !b) return KZK_ERR_ARG;
     if (node < 0 || (p->steps_limit >= 0 && node > p->steps_limit)) return KZK_ERR_STATE;
     if (tau(p, 0, u, nullptr, nullptr, p->dC, 0) != hipSuccess) return KZK_ERR_DEVICE;
-    if (tau(p, 2, nullptr, nullptr, p->dC, p->dB, node) != hipSuccess) return KZK_ERR_DEVICE;
+    kzk_status st = stage_b(p, node);
+    if (st != KZK_OK) return st;
     // the tau-pass leaves the spectrum of the face fluxes: apply the difference
+    // (and add the transverse part of b with transport)
+    const void* by = p->transport ? p->dBys : nullptr;
     for (int i = 0; i < p->n_inst; ++i) {
         const long long n = (long long)p->desc[i].M * p->desc[i].n_y;
-        if ((p->dtype == KZK_F32 ? kzk::launch_flux_diff<float>(p->dDesc, i, n, p->dB, p->stream)
-                                 : kzk::launch_flux_diff<double>(p->dDesc, i, n, p->dB, p->stream)) != hipSuccess)
+        if ((p->dtype == KZK_F32 ? kzk::launch_flux_diff<float>(p->dDesc, i, n, p->dB, by, p->stream)
+                                 : kzk::launch_flux_diff<double>(p->dDesc, i, n, p->dB, by, p->stream)) != hipSuccess)
             return KZK_ERR_DEVICE;
     }
     if (tau(p, 1, nullptr, b, p->dB, nullptr, 0) != hipSuccess) return KZK_ERR_DEVICE;
@@ -878,7 +990,7 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
 extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
-    if (p->scheme != 0 || p->any_reg) return KZK_ERR_ARG;   // the adjoint is of ExpRK22, mean mode zeroed
+    if (p->scheme != 0 || p->any_reg || p->transport) return KZK_ERR_ARG;   // ExpRK22, zeroed mean, Burgers b
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

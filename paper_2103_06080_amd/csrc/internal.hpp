@@ -33,6 +33,13 @@ struct InstDesc {
     double dtau, h, L_tau, L_y, A, weno_eps;
     double D_const, nl_const, cfl_max;
     double reg_eps;          // > 0: regularised multiplier, 1/(i kt) -> 1/(i kt + reg_eps/(4 pi))
+    // transport by the random velocity field (vel = 1): per node x_n of the
+    // schedule, vel_tab[n][0..2][j] = U_par, U_perp, d_y U_perp at y_j (FP64)
+    // and vel_amax[n] = max_j |U_perp|, the LF speed along y
+    int vel, pad1;
+    double y0, dy;
+    const double* vel_tab;
+    const double* vel_amax;
     const double* nl_node;   // device [n_steps_max+1] or nullptr -> nl_const
     const double* D_step;    // device [n_steps_max]   or nullptr -> D_const
     // device [M] complex (working precision): flux-difference symbol sigma_m
@@ -42,6 +49,10 @@ struct InstDesc {
 
 struct TauItem { int inst, row0; };
 struct YItem { int inst, m0; };
+// transverse WENO5 pass: 256 tau-points from k0, YW_SEG rows from j0
+struct YwItem { int inst, k0, j0; };
+constexpr int YW_SEG = 32;
+constexpr int YW_THREADS = 256;
 
 // Launchers (kernels.hip).  All enqueue on `s` and return hipSuccess or the
 // launch error.  tw: twiddles exp(-2 pi i k / 2^log2_ntw); twst: per-stage
@@ -60,10 +71,25 @@ bool tau_threads_supported(int dtype_is_f64, int nt);
 // whose multipliers the y-pass computes itself (those with D_step; stage 1
 // then writes their h Phi2 table for stage 2).  full: every instance has
 // W n_y = 16 nt and n_y >= 512 (full tiles; progression addressing).
+// By: tau-spectrum of the transverse transport part of b (instances with
+// vel = 1; nullptr otherwise), added to sigma_m B before the y-transform.
 template <typename T>
 hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
-                    hipStream_t s);
+                    int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+                    const void* twst, int step, hipStream_t s);
+
+// Transverse part of b on the physical field u at node `node`:
+// by = -(G_{j+1/2} - G_{j-1/2}) / dy + (d_y U_perp)_j u_j, G the WENO5/LF flux
+// of g = U_perp u along y (instances with vel = 1).
+template <typename T>
+hipError_t launch_yweno(const InstDesc* d_desc, const YwItem* d_items, int n_items, const T* u, T* by, int node,
+                        unsigned* status, hipStream_t s);
+
+// Velocity tables of one instance for nodes 0 .. n_nodes-1 (FP64), from the
+// per-mode wavenumber K_n lambda, amplitude, cos and sin of the angle, and
+// phase (modes[5][n_modes]).
+hipError_t launch_velocity(const InstDesc* d_desc, int inst, const double* modes, int n_modes, double x0, double h,
+                           int n_nodes, double* tab, double* amax, hipStream_t s);
 // blocks of the y-pass kernels (block size nt, full-tile variant or not)
 // resident at once on the device
 int y_resident_blocks(int dtype_is_f64, int nt, int full, int device);
@@ -72,17 +98,21 @@ template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,
                          hipStream_t s);
 
-// b^ = sigma_m F^ in place on instance inst's tiled tau-spectrum (n = M n_y
+// b^ = sigma_m F^ (+ Y, the spectrum of the transverse transport part, when
+// Y is not null) in place on instance inst's tiled tau-spectrum (n = M n_y
 // elements): the flux difference applied to a tau-pass result.
 template <typename T>
-hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, hipStream_t s);
+hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, const void* Y, hipStream_t s);
 
-// Mean tau-mode column of the regularised multiplier, after y-pass stage 1:
-// C~*(0, y) and P(0, y) := F_y^-1 [E_0(ky) F_y U(0, .)] for the instances
-// with reg_eps > 0 (one block per instance; the others return at once).
+// Mean tau-mode column of the regularised multiplier (instances with
+// reg_eps > 0; one block per instance, the others return at once), after
+// y-pass stage 1: C~*(0, .) = F_y^-1[E_0 U^ + h Phi1_0 b^], P(0, .) =
+// F_y^-1[E_0 U^ + h (Phi1_0 - Phi2_0) b^]; after stage 2 (transport only):
+// U(0, .) = C~(0, .) = P(0, .) + F_y^-1[h Phi2_0 b*^].  b^ is the y-transform
+// of the mean of b (By column 0), zero without transport.
 template <typename T>
-hipError_t launch_dc(const InstDesc* d_desc, int n_inst, void* C, void* P, const void* U, const void* twst, int step,
-                     hipStream_t s);
+hipError_t launch_dc(int stage, const InstDesc* d_desc, int n_inst, void* C, void* P, void* U, const void* By,
+                     const void* twst, int step, hipStream_t s);
 
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,

@@ -492,10 +492,32 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
         }
     }
     mx = line_max(mx, tpr, redT);
-    const bool bad = !finite_val(mx);
+    bool bad = !finite_val(mx);
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
     const T nlT = (T)nl;
-    const T alpha = (T)fabs(nl) * mx;
+    T alpha = (T)fabs(nl) * mx;
+    // transport: the tau-flux is nl u^2/2 - c u with c = 2 pi U_par(x_node, y_row),
+    // so f' = nl u - c and alpha = max_k |nl u_k - c| = max(|nl max u - c|, |nl min u - c|)
+    T cpar = 0;
+    if (d.vel) {
+        cpar = (T)(2.0 * KZK_PI * d.vel_tab[(size_t)node * 3 * d.n_y + (row < d.n_y ? row : 0)]);
+        T hi = -mx, lo = -mx;             // max u and max(-u), NaN-propagating like mx
+        if (active) {
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const quad<T> v = lds_quad(lds, base, t + q * tpr);
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    hi = nmax(hi, v.v[i]);
+                    lo = nmax(lo, -v.v[i]);
+                }
+            }
+        }
+        hi = line_max(hi, tpr, redT);
+        lo = line_max(lo, tpr, redT);
+        alpha = tmax((T)fabs(nlT * hi - cpar), (T)fabs(nlT * -lo - cpar));
+        bad = bad || !finite_val(alpha);
+    }
     if (active && t == 0) {
         unsigned f = 0;
         if (bad) f |= ST_NONFINITE;
@@ -505,7 +527,8 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
 
     // ---- WENO5 fluxes at the faces 8g + k + 1/2 (k < 8) of my groups g = t + q*tpr (q < 4)
     const T eps = (T)d.weno_eps;
-    const T nlq = (T)0.25 * nlT, ha = (T)0.5 * alpha;
+    // split fluxes f+- = (nl u^2/2 - c u +- alpha u)/2 = u (nl u/4 + (+-alpha - c)/2)
+    const T nlq = (T)0.25 * nlT, ha = (T)0.5 * (alpha - cpar);
     T F[4][8];
     #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -645,47 +668,185 @@ __device__ __forceinline__ void nyquist_multipliers(const InstDesc& d, T& E, T& 
     P2 = (T)(h * p2.x);
 }
 
+// ------------------------------------------------------------------ transverse transport (Sec. 3.4 eq. (21)-(22))
+// by_j = -(G_{j+1/2} - G_{j-1/2}) / dy + (d_y U_perp)_j u_j along every y-line
+// of the physical field u, G the WENO5-JS flux with Lax-Friedrichs splitting
+// of g_j = U_perp(x_node, y_j) u_j, speed alpha = max_j |U_perp| (g' does not
+// depend on u): G = F+ + F-, F+ from g+ = (g + alpha u)/2 on rows j-2..j+2,
+// F- from g- = (g - alpha u)/2 on the mirrored rows j+3..j-1.  A block of
+// YW_THREADS threads takes YW_THREADS consecutive tau-points (one column
+// each, coalesced) and YW_SEG rows from j0; it stages the rows j0-3 ..
+// j0+YW_SEG+2 of its columns (periodic in y) in LDS, then each thread sweeps
+// its column computing every face once.
+template <typename T>
+__global__ __launch_bounds__(YW_THREADS) void yweno_kernel(const InstDesc* __restrict__ descs,
+                                                           const YwItem* __restrict__ items, const T* __restrict__ u,
+                                                           T* __restrict__ by, int node, unsigned* __restrict__ status) {
+    constexpr int R = YW_SEG + 6;
+    __shared__ T us[R][YW_THREADS];
+    __shared__ T vp[R], vd[YW_SEG];
+    const YwItem it = items[blockIdx.x];
+    const InstDesc& d = descs[it.inst];
+    const int nt = d.n_tau, ny = d.n_y, tid = threadIdx.x;
+    const int k = it.k0 + tid, j0 = it.j0;
+    const bool act = k < nt;
+    const double* vt = d.vel_tab + (size_t)node * 3 * ny;
+    if (tid < R) vp[tid] = (T)vt[ny + ((j0 - 3 + tid) & (ny - 1))];
+    if (tid < YW_SEG) vd[tid] = (T)vt[2 * ny + ((j0 + tid) & (ny - 1))];
+    const T* uc = u + d.off_u + (act ? k : 0);
+    #pragma unroll
+    for (int r = 0; r < R; ++r) us[r][tid] = uc[(size_t)((j0 - 3 + r) & (ny - 1)) * nt];
+    const T ay = (T)d.vel_amax[node];
+    if (blockIdx.x == 0 && tid == 0 && (double)ay * d.h > d.cfl_max * d.dy) atomicOr(status, ST_CFL);
+    __syncthreads();
+    if (!act) return;
+    const T eps = (T)d.weno_eps, idy = (T)(1.0 / d.dy);
+    auto gp = [&](int r) -> T { const T x = us[r][tid]; return (T)0.5 * (vp[r] * x + ay * x); };
+    auto gm = [&](int r) -> T { const T x = us[r][tid]; return (T)0.5 * (vp[r] * x - ay * x); };
+    // face j0 - 1/2 (rows j0-3 .. j0+2 = r 0..5)
+    T Gm = weno_face(gp(0), gp(1), gp(2), gp(3), gp(4), eps) + weno_face(gm(5), gm(4), gm(3), gm(2), gm(1), eps);
+    T* bc = by + d.off_u + k;
+    const int nj = min(YW_SEG, ny - j0);
+    for (int i = 0; i < nj; ++i) {
+        // face j0 + i + 1/2: rows r = i+1 .. i+6
+        const T G = weno_face(gp(i + 1), gp(i + 2), gp(i + 3), gp(i + 4), gp(i + 5), eps) +
+                    weno_face(gm(i + 6), gm(i + 5), gm(i + 4), gm(i + 3), gm(i + 2), eps);
+        bc[(size_t)(j0 + i) * nt] = vd[i] * us[i + 3][tid] - (G - Gm) * idy;
+        Gm = G;
+    }
+}
+
+// Velocity tables (Sec. 2, Algorithm 1) of one instance at the nodes
+// x_n = x0 + n h and rows y_j, evaluated in FP64 in Cartesian form:
+// with K_n . r = (K_n lambda)(x cos theta_n + y sin theta_n) + phi_n and
+// U~_n = a_n (-sin theta_n, cos theta_n),
+//   U_par = sum -a_n sin theta_n cos(.),  U_perp = sum a_n cos theta_n cos(.),
+//   d_y U_perp = -sum a_n cos theta_n (K_n lambda) sin theta_n sin(.).
+// modes: [5][n_modes] = K_n lambda, a_n, cos theta_n, sin theta_n, phi_n.
+// Block (j-range, node).
+__global__ __launch_bounds__(256) void velocity_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                       const double* __restrict__ modes, int n_modes, double x0,
+                                                       double h, double* __restrict__ tab) {
+    const InstDesc& d = descs[inst];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, n = blockIdx.y, ny = d.n_y;
+    if (j >= ny) return;
+    const double x = x0 + h * n, y = d.y0 + d.dy * j;
+    const double* kl = modes;
+    const double* am = modes + n_modes;
+    const double* cth = modes + 2 * n_modes;
+    const double* sth = modes + 3 * n_modes;
+    const double* ph = modes + 4 * n_modes;
+    double a = 0, p = 0, dp = 0;
+    for (int m = 0; m < n_modes; ++m) {
+        double sp, cp;
+        sincos(kl[m] * (x * cth[m] + y * sth[m]) + ph[m], &sp, &cp);
+        a -= am[m] * sth[m] * cp;
+        p += am[m] * cth[m] * cp;
+        dp -= am[m] * cth[m] * kl[m] * sth[m] * sp;
+    }
+    double* o = tab + (size_t)n * 3 * ny;
+    o[j] = a;
+    o[ny + j] = p;
+    o[2 * ny + j] = dp;
+}
+
+// max_j |U_perp(x_n, y_j)| per node (one block per node)
+__global__ __launch_bounds__(256) void velocity_max_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                           const double* __restrict__ tab,
+                                                           double* __restrict__ amax) {
+    __shared__ double red[4];
+    const InstDesc& d = descs[inst];
+    const int n = blockIdx.x, ny = d.n_y;
+    const double* p = tab + (size_t)n * 3 * ny + ny;
+    double m = 0;
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) m = fmax(m, fabs(p[j]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) amax[n] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 // ------------------------------------------------------------------ mean tau-mode (regularised multiplier)
 // With the regularised multiplier the mean tau-mode of wavenumber ky has the
 // real symbol l_0 = -(Dbar/2) ky^2 (4 pi / eps).  Column 0 of the spectral
 // arrays holds the mean mode (.x) and the tau-Nyquist mode (.y) of every row
-// in y-physical form; the y-pass keeps the mean as it is.  After stage 1 this
-// kernel applies E_0 along y to the state's mean column,
-//     C~*(0, .) = P(0, .) = F_y^-1 [ E_0 F_y U(0, .) ],
-// which is the whole stage-1 update of that column: the flux difference of b
-// has no mean (sigma_0 = 0), so the Phi terms vanish there; stage 2 then
-// copies P(0, .) to the state as before (U = P + h Phi2 * 0).  One block per
-// instance; the FFT runs on the n_y/16 first threads.
-template <typename T>
+// in y-physical form; the y-pass leaves the mean as it is (the Nyquist part
+// it updates pointwise).  This kernel applies the multipliers of l_0 along y:
+//   after stage 1:  C~*(0, .) = F^-1[E_0 U^ + h Phi1_0 b^],
+//                   P(0, .)   = F^-1[E_0 U^ + h (Phi1_0 - Phi2_0) b^],
+//   after stage 2:  U(0, .) = C~(0, .) = P(0, .) + F^-1[h Phi2_0 b*^],
+// U^ the y-transform of the state's mean column, b^ that of the mean of b.
+// The flux difference of the Burgers and axial terms has no mean (sigma_0 =
+// 0), so b^ comes from the transverse transport part only (By column 0) and
+// is zero without transport (stage 2 then has nothing to do).  Two real
+// columns share one complex transform each way: z = U + i b forward, and
+// C~* + i P backward.  One block per instance; the FFT runs on the first
+// n_y/16 threads.
+template <typename T, int STAGE>
 __global__ __launch_bounds__(256) void dc_kernel(const InstDesc* __restrict__ descs, cpx<T>* __restrict__ C,
-                                                 cpx<T>* __restrict__ P, const cpx<T>* __restrict__ U,
-                                                 const cpx<T>* __restrict__ twst, int step) {
+                                                 cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
+                                                 const cpx<T>* __restrict__ By, const cpx<T>* __restrict__ twst,
+                                                 int step) {
     __shared__ alignas(32) cpx<T> lds[padded(4096)];
     const InstDesc& d = descs[blockIdx.x];
     if (!(d.reg_eps > 0.0)) return;
+    const bool tb = d.vel != 0 && By != nullptr;
+    if (STAGE == 2 && !tb) return;
     const int Ny = d.n_y, W = d.W, tid = threadIdx.x;
     const long long o = d.off_state;             // tile 0: element (y, column 0) at y W
-    for (int y = tid; y < Ny; y += blockDim.x) lds[padi(y)] = cpx<T>{U[o + (long long)y * W].x, (T)0};
+    for (int y = tid; y < Ny; y += blockDim.x) {
+        const long long e = o + (long long)y * W;
+        const T b = tb ? By[e].x : (T)0;
+        lds[padi(y)] = STAGE == 1 ? cpx<T>{U[e].x, b} : cpx<T>{b, (T)0};
+    }
     __syncthreads();
     const bool act = tid < (Ny >> 4);
     lds_fft<T, -1>(lds, 0, Ny, tid, act, twst);
     __syncthreads();
     const double Dbar = d.D_step ? d.D_step[step] : d.D_const;
     const double dl = d.reg_eps / (4.0 * KZK_PI);
-    for (int n = tid; n < Ny; n += blockDim.x) {
-        const int ns = n <= (Ny >> 1) ? n : Ny - n;
-        const double ky = 2.0 * KZK_PI * (double)ns / d.L_y;
-        // E_0 = exp(h l_0) (0 for the large |z| of a small eps), and 1/n_y of the inverse transform
-        const T e = (T)(exp(-d.h * 0.5 * Dbar * ky * ky / dl) / (double)Ny);
-        lds[padi(n)] = e * lds[padi(n)];
+    const double s = 1.0 / (double)Ny;           // of the inverse transform
+    // pairs (n, Ny - n): Z_n = A_n + i B_n with A, B the spectra of the two real columns
+    for (int n = tid; n <= (Ny >> 1); n += blockDim.x) {
+        const int nm = (Ny - n) & (Ny - 1);
+        const double ky = 2.0 * KZK_PI * (double)n / d.L_y;
+        cpx<double> e, p1, p2;
+        phis_f64(-d.h * 0.5 * Dbar * ky * ky / dl, 0.0, e, p1, p2);
+        const T E0 = (T)(e.x * s), H1 = (T)(d.h * p1.x * s), H2 = (T)(d.h * p2.x * s);
+        const cpx<T> zn = lds[padi(n)], zm = lds[padi(nm)];
+        // A_n = (Z_n + conj Z_{-n})/2, B_n = (Z_n - conj Z_{-n})/(2i), and the same at -n
+        const cpx<T> An = {(T)0.5 * (zn.x + zm.x), (T)0.5 * (zn.y - zm.y)};
+        const cpx<T> Bn = {(T)0.5 * (zn.y + zm.y), (T)0.5 * (zm.x - zn.x)};
+        const cpx<T> Am = conj(An), Bm = conj(Bn);
+        cpx<T> wn, wm;
+        if (STAGE == 1) {
+            // W = (E_0 A + H1 B) + i (E_0 A + (H1 - H2) B)
+            const cpx<T> u1 = E0 * An + H1 * Bn, q1 = E0 * An + (H1 - H2) * Bn;
+            const cpx<T> u2 = E0 * Am + H1 * Bm, q2 = E0 * Am + (H1 - H2) * Bm;
+            wn = u1 + mul_si<1>(q1);
+            wm = u2 + mul_si<1>(q2);
+        } else {
+            // W = H2 A (the transform of b* sits in A)
+            wn = H2 * An;
+            wm = H2 * Am;
+        }
+        lds[padi(n)] = wn;
+        if (nm != n) lds[padi(nm)] = wm;
     }
     __syncthreads();
     lds_fft<T, 1>(lds, 0, Ny, tid, act, twst);
     __syncthreads();
     for (int y = tid; y < Ny; y += blockDim.x) {
-        const T v = lds[padi(y)].x;
-        C[o + (long long)y * W].x = v;
-        P[o + (long long)y * W].x = v;
+        const long long e = o + (long long)y * W;
+        const cpx<T> w = lds[padi(y)];
+        if (STAGE == 1) {
+            C[e].x = w.x;
+            P[e].x = w.y;
+        } else {
+            const T v = P[e].x + w.x;
+            C[e].x = v;
+            U[e].x = v;
+        }
     }
 }
 
@@ -777,8 +938,8 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 template <typename T, int NT, int STAGE, bool FULL>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
-        const cpx<T>* __restrict__ B, cpx<T>* __restrict__ P, cpx<T>* __restrict__ U, cpx<T>* __restrict__ tabs,
-        const cpx<T>* __restrict__ twst, int step) {
+        const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
+        cpx<T>* __restrict__ tabs, const cpx<T>* __restrict__ twst, int step) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16) + (FULL ? NT : 0)];
     constexpr unsigned E = sizeof(cpx<T>);
     const int tid = threadIdx.x;
@@ -823,8 +984,12 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     const int s1 = colbase(c) + padi(Ny - j0);          // slot of row Ny - j0 (q = 0)
     const bool keep_c = !(col0 && c == 0);
     // the tau-pass leaves the spectrum of the face fluxes; b^ = sigma F^ (the
-    // column of a thread's combine items is tid mod W in both paths)
-    const cpx<T> sg = STAGE > 0 ? flux_diff_symbol<T>(d, m0 + c) : cpx<T>{(T)0, (T)0};
+    // column of a thread's combine items is tid mod W in both paths).  With
+    // transport the transverse part By (a spectrum of b itself) is added at
+    // the tile load, sigma F^ + By, and the combine multiplies by 1.
+    const bool tr = STAGE > 0 && By != nullptr && d.vel != 0;
+    const cpx<T> sgl = STAGE > 0 ? flux_diff_symbol<T>(d, m0 + c) : cpx<T>{(T)0, (T)0};
+    const cpx<T> sg = tr ? cpx<T>{(T)1, (T)0} : sgl;
     cpx<T>* fbuf = FULL ? lds + colbase(fc) : lds;      // this thread's FFT column
     const int fbase = FULL ? 0 : fc * Ny;
 
@@ -838,6 +1003,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         }
     } else {
         tile_fetch<T, NT>(src + to, ne, tid, vr, vi);
+    }
+    if (tr) {
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpx<T> y = By[to + min(tid + q * NT, ne - 1)];
+            const cpx<T> x = cmul(sgl, cpx<T>{vr[q], vi[q]}) + y;
+            vr[q] = x.x;
+            vi[q] = x.y;
+        }
     }
     if (Ny != tw_ny) {
         lds_fft_twiddles<T>(Ny, ft, twst, ytw);
@@ -1111,7 +1285,9 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         const T sN = (T)(-2.0 / d.dtau);                  // sigma at the tau-Nyquist mode
         for (int y = tid; y < Ny; y += NT) {
             const long long o = (long long)y * W;
-            const cpx<T> b = {(T)0, sN * Bt[o].y};          // the DC of b is zero
+            // the mean mode (.x) is left to the DC path: zeroed F(b)(0, .), or
+            // the mean-column kernel of the regularised multiplier
+            const cpx<T> b = {(T)0, sN * Bt[o].y + (tr ? By[to + o].y : (T)0)};
             if (STAGE == 1) {
                 const cpx<T> cr = Ut[o];
                 Ct[o] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
@@ -1555,21 +1731,25 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
 
 template <typename T, int NT, bool FULL>
 static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                              void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
-                              hipStream_t s) {
+                              void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
+                              int step, hipStream_t s) {
     dim3 g(max_blocks > 0 && max_blocks < n_items ? max_blocks : n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
+    const cpx<T>* by = static_cast<const cpx<T>*>(By);
     cpx<T>* p = static_cast<cpx<T>*>(P);
     cpx<T>* u = static_cast<cpx<T>*>(U);
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
+                           step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
+                           step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, p, u, tb, ws, step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
+                           step);
     return hipGetLastError();
 }
 
@@ -1606,16 +1786,18 @@ bool y_threads_supported(int is_f64, int nt) {
 
 template <typename T, bool FULL>
 static hipError_t launch_y_full(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                                int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst,
-                                int step, hipStream_t s) {
+                                int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+                                const void* twst, int step, hipStream_t s) {
     switch (nt) {
     case 256:
-        return launch_y_nt<T, 256, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
+        return launch_y_nt<T, 256, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+                                         step, s);
     case 512:
-        return launch_y_nt<T, 512, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst, step, s);
+        return launch_y_nt<T, 512, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+                                         step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+            return launch_y_nt<T, 1024, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                               step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
@@ -1624,12 +1806,12 @@ static hipError_t launch_y_full(int stage, int nt, const InstDesc* d_desc, const
 
 template <typename T>
 hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    int max_blocks, void* C, const void* B, void* P, void* U, void* tabs, const void* twst, int step,
-                    hipStream_t s) {
+                    int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+                    const void* twst, int step, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    return full ? launch_y_full<T, true>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+    return full ? launch_y_full<T, true>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                          step, s)
-                : launch_y_full<T, false>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, P, U, tabs, twst,
+                : launch_y_full<T, false>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                           step, s);
 }
 
@@ -1638,33 +1820,60 @@ hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const Y
 // m = (e / (W n_y)) W + e mod W; slot m = 0 holds (DC, Nyquist)).
 template <typename T>
 __global__ __launch_bounds__(256) void flux_diff_kernel(const InstDesc* __restrict__ descs, int inst,
-                                                        cpx<T>* __restrict__ X) {
+                                                        cpx<T>* __restrict__ X, const cpx<T>* __restrict__ Y) {
     const InstDesc& d = descs[inst];
     const long long n = (long long)d.M * d.n_y, tile = (long long)d.W * d.n_y;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         const int m = (int)((e / tile) * d.W + (e & (d.W - 1)));
         cpx<T>& x = X[d.off_state + e];
-        if (m == 0) x = cpx<T>{(T)0, (T)(-2.0 / d.dtau) * x.y};
-        else x = cmul(flux_diff_symbol<T>(d, m), x);
+        cpx<T> r = m == 0 ? cpx<T>{(T)0, (T)(-2.0 / d.dtau) * x.y} : cmul(flux_diff_symbol<T>(d, m), x);
+        if (Y) r = r + Y[d.off_state + e];
+        x = r;
     }
 }
 
 template <typename T>
-hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, hipStream_t s) {
+hipError_t launch_flux_diff(const InstDesc* d_desc, int inst, long long n, void* X, const void* Y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const long long blocks = (n + 255) / 256;
     dim3 g((unsigned)(blocks < 4096 ? blocks : 4096)), b(256);
-    hipLaunchKernelGGL((flux_diff_kernel<T>), g, b, 0, s, d_desc, inst, static_cast<cpx<T>*>(X));
+    hipLaunchKernelGGL((flux_diff_kernel<T>), g, b, 0, s, d_desc, inst, static_cast<cpx<T>*>(X),
+                       static_cast<const cpx<T>*>(Y));
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dc(const InstDesc* d_desc, int n_inst, void* C, void* P, const void* U, const void* twst, int step,
-                     hipStream_t s) {
+hipError_t launch_dc(int stage, const InstDesc* d_desc, int n_inst, void* C, void* P, void* U, const void* By,
+                     const void* twst, int step, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL((dc_kernel<T>), dim3(n_inst), dim3(256), 0, s, d_desc, static_cast<cpx<T>*>(C),
-                       static_cast<cpx<T>*>(P), static_cast<const cpx<T>*>(U), static_cast<const cpx<T>*>(twst),
-                       step);
+    cpx<T>* c = static_cast<cpx<T>*>(C);
+    cpx<T>* p = static_cast<cpx<T>*>(P);
+    cpx<T>* u = static_cast<cpx<T>*>(U);
+    const cpx<T>* b = static_cast<const cpx<T>*>(By);
+    const cpx<T>* w = static_cast<const cpx<T>*>(twst);
+    if (stage == 1)
+        hipLaunchKernelGGL((dc_kernel<T, 1>), dim3(n_inst), dim3(256), 0, s, d_desc, c, p, u, b, w, step);
+    else
+        hipLaunchKernelGGL((dc_kernel<T, 2>), dim3(n_inst), dim3(256), 0, s, d_desc, c, p, u, b, w, step);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_yweno(const InstDesc* d_desc, const YwItem* d_items, int n_items, const T* u, T* by, int node,
+                        unsigned* status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((yweno_kernel<T>), dim3(n_items), dim3(YW_THREADS), 0, s, d_desc, d_items, u, by, node, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity(const InstDesc* d_desc, int inst, const double* modes, int n_modes, double x0, double h,
+                           int n_nodes, double* tab, double* amax, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    // the host passes n_y through the descriptor; 4096 rows at most
+    hipLaunchKernelGGL(velocity_kernel, dim3(16, n_nodes), dim3(256), 0, s, d_desc, inst, modes, n_modes, x0, h, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(velocity_max_kernel, dim3(n_nodes), dim3(256), 0, s, d_desc, inst, tab, amax);
     return hipGetLastError();
 }
 
@@ -1752,10 +1961,13 @@ void stage_twiddles(double* out) {
     template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
                                       void*, const void*, const void*, int, int, int, int, unsigned*, hipStream_t);  \
     template hipError_t launch_y<T>(int, int, int, const InstDesc*, const YItem*, int, int, void*, const void*,     \
-                                    void*, void*, void*, const void*, int, hipStream_t);                             \
+                                    const void*, void*, void*, void*, const void*, int, hipStream_t);                \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
-    template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, hipStream_t);                    \
-    template hipError_t launch_dc<T>(const InstDesc*, int, void*, void*, const void*, const void*, int, hipStream_t); \
+    template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, const void*, hipStream_t);       \
+    template hipError_t launch_dc<T>(int, const InstDesc*, int, void*, void*, void*, const void*, const void*, int,   \
+                                     hipStream_t);                                                                   \
+    template hipError_t launch_yweno<T>(const InstDesc*, const YwItem*, int, const T*, T*, int, unsigned*,           \
+                                        hipStream_t);                                                                \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, unsigned*,            \
                                           hipStream_t);                                                              \

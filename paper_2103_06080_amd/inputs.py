@@ -264,6 +264,35 @@ def medium(seed: int, n_modes: int = 200) -> dict:
     return dict(vel=1, vel_modes=n_modes, vel_phi=u[:, 0].copy(), vel_theta=u[:, 1].copy())
 
 
+# Table 0 of the paper (N_sigma, N_rho, N_theta) and the power-of-two grids
+# that stand in for them here (n_tau x n_y = theta x rho)
+PAPER_SETS = {1: (300, 1250, 448), 2: (600, 2500, 896), 3: (1200, 5000, 1792), 4: (2400, 10000, 3584)}
+PAPER_SET_GRIDS = {1: (512, 1024), 2: (1024, 2048), 3: (2048, 4096)}
+
+
+def paper_set(k: int, seed: int = 0, n_modes: int = 200, reg_eps: float = 2.0 ** -24,
+              n_steps: Optional[int] = None) -> Problem:
+    """The paper's workload (Sec. 4) on the power-of-two grid nearest to set k
+    of Table 0: sigma in [0, 120] with N_sigma steps, rho in [0, 400),
+    theta in [-13 pi, 15 pi), D/2 = 1/(4 pi), B = 0.05 (nl = -B), A = 3.4e-4,
+    the random medium of Sec. 2 (seeded phases and angles), the regularised
+    multiplier, and the paper's N-wave
+    V0 = (theta - 3 pi)/(2 pi) (tanh(B/(4A)(theta - 4 pi)) - tanh(B/(4A)(theta - 2 pi)))."""
+    n_sigma, _, _ = PAPER_SETS[k]
+    n_tau, n_y = PAPER_SET_GRIDS[k]
+    ns = n_sigma if n_steps is None else n_steps
+    B, A = 0.05, 3.4e-4
+    p = Problem(name="paper_set%d" % k, n_tau=n_tau, n_y=n_y, h=120.0 / n_sigma, n_steps=ns,
+                D_step=np.full(ns, 1.0 / (2 * math.pi)), nl_node=np.full(ns + 1, -B), u0=np.zeros((1, 1)),
+                tau0=-13 * math.pi, L_tau=28 * math.pi, y0=0.0, L_y=400.0, A=A,
+                D_const=1.0 / (2 * math.pi), nl_const=-B, reg_eps=reg_eps, **medium(seed, n_modes))
+    th = p.tau()
+    v = (th - 3 * math.pi) / (2 * math.pi) * (np.tanh(B / (4 * A) * (th - 4 * math.pi)) -
+                                              np.tanh(B / (4 * A) * (th - 2 * math.pi)))
+    p.u0 = np.tile(v, (n_y, 1))
+    return p
+
+
 def fd_direction(r: int, shape) -> np.ndarray:
     """Finite-difference direction r of the adjoint workload: N(0,1), seed 1000 + r."""
     n = int(np.prod(shape))

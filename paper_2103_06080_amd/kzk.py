@@ -24,7 +24,7 @@ EXPORTS = ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_inst_offset
            "kzk_eval_b", "kzk_tau_forward", "kzk_tau_inverse", "kzk_profile_enable", "kzk_profile_read",
            "kzk_read_tables", "kzk_autotune", "kzk_step_noalloc", "kzk_set_tau_threads",
            "kzk_get_tau_threads"]
-KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "other"]
+KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "transport"]
 
 
 class KZKError(RuntimeError):
@@ -49,6 +49,13 @@ class Params(ctypes.Structure):
         ("cfl_max", ctypes.c_double),
         ("scheme", ctypes.c_int32),
         ("reg_eps", ctypes.c_double),
+        ("vel", ctypes.c_int32),
+        ("vel_modes", ctypes.c_int32),
+        ("vel_phi", ctypes.POINTER(ctypes.c_double)),
+        ("vel_theta", ctypes.POINTER(ctypes.c_double)),
+        ("vel_lambda", ctypes.c_double),
+        ("vel_sigma_u", ctypes.c_double),
+        ("vel_c0", ctypes.c_double),
     ]
 
 
@@ -124,11 +131,31 @@ def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None
         D_ptr = D.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         nl_ptr = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         nmax = len(D)
+    vel = int(getattr(p, "vel", 0))
+    vphi = vtheta = null
+    if vel:
+        if vel != 1:
+            raise ValueError("the library takes vel = 0 or 1")
+        a = np.ascontiguousarray(p.vel_phi, dtype=np.float64)
+        b = np.ascontiguousarray(p.vel_theta, dtype=np.float64)
+        D = np.ascontiguousarray(p.D_step, dtype=np.float64)
+        nl = np.ascontiguousarray(p.nl_node, dtype=np.float64)
+        if keep is not None:
+            keep += [a, b, D, nl]
+        vphi = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        vtheta = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if not nmax:   # the field is tabulated at the nodes of the schedule
+            D_ptr = D.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            nl_ptr = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            nmax = len(D)
     return Params(p.n_tau, p.n_y, p.tau0, p.L_tau, p.y0, p.L_y, p.x0, p.h, dtype,
                   float(p.D_const if p.D_const is not None else 0.0), p.A,
                   float(p.nl_const if p.nl_const is not None else 0.0),
                   D_ptr, nl_ptr, nmax, p.lf_scope, p.weno_eps, cfl_max,
-                  int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)))
+                  int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)),
+                  vel, int(getattr(p, "vel_modes", 0)), vphi, vtheta,
+                  float(getattr(p, "vel_lambda", 0.0)), float(getattr(p, "vel_sigma_u", 0.0)),
+                  float(getattr(p, "vel_c0", 0.0)))
 
 
 def step_noalloc(problems, u, first: int = 0, n_steps: int = 1, dtype: str = "f64", stream=None,

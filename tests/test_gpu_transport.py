@@ -1,0 +1,122 @@
+"""GPU parity of the transport terms (the full inhomogeneous b of Sec. 3.3
+eq. (16) in the conservative form of Sec. 3.4 eq. (21)-(22), with the random
+velocity field of Sec. 2, Algorithm 1) with the FP64 oracle: b itself on
+smooth and rough fields, marches with both schemes and both treatments of the
+mean tau-mode, on general and full-tile y-passes, and the paper's workload on
+the power-of-two grid that stands in for set 1 of Table 0.
+
+Bars: FP64 <= 1e-12 relative l2 (marches and b), FP32 <= 1e-4 for marches;
+the largest pointwise error <= the same factor times max|u|.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2103_06080_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-4}
+EPS = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def max_rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def medium_case(nt, ny, n_steps, h=2e-3, seed=3, sched=False, scheme=0, reg=0.0, rough=False, nl=0.9, A=1e-4):
+    p = I.Problem(name="m", n_tau=nt, n_y=ny, h=h, n_steps=n_steps,
+                  D_step=np.full(n_steps, 0.05), nl_node=np.full(n_steps + 1, nl),
+                  u0=np.zeros((ny, nt)), A=A, D_const=0.05, nl_const=nl, x0=1.5,
+                  scheme=scheme, reg_eps=reg, **I.medium(seed, 200))
+    if rough:
+        p.u0 = I.random_field(seed + 100, (ny, nt)) * 0.8
+    else:
+        rng = I.SplitMix64(seed)
+        T, a, modes = I._draw_nwave(rng)
+        p.u0 = I.nwave(p.tau(), p.y(), T, a, 0.1, modes, p.y0, p.L_y) + 0.1
+    if sched:
+        p.D_step = 0.05 * (1.0 + 0.3 * np.sin(1.0 + np.arange(n_steps)))
+        p.nl_node = nl * (1.0 + 0.2 * np.cos(np.arange(n_steps + 1)))
+        p = dataclasses.replace(p, D_const=None, nl_const=None)
+    return p
+
+
+def march(p, dtype, y_threads=None):
+    from paper_2103_06080_amd import kzk
+    plan = kzk.Plan(p, dtype=dtype, y_threads=y_threads)
+    u = plan.pack([p.u0])
+    plan.step(u, 0, p.n_steps)
+    assert plan.poll() == 0
+    got = plan.unpack(u)[0]
+    plan.close()
+    return got
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt,ny,rough", [(64, 16, False), (256, 64, True), (1024, 128, False), (128, 512, True)])
+def test_transport_b_matches_oracle(torch_cuda, orc, dtype, nt, ny, rough):
+    from paper_2103_06080_amd import kzk
+    p = medium_case(nt, ny, 3, rough=rough)
+    plan = kzk.Plan(p, dtype=dtype)
+    node = 2
+    b = plan.eval_b(plan.pack([p.u0]), node).double().cpu().numpy().reshape(ny, nt)
+    ref = orc.eval_b(p, p.x0 + node * p.h, p.nl_node[node], p.u0)
+    e2, em = rel_l2(b, ref), max_rel(b, ref)
+    print("transport b %s %dx%d rough=%s: rel l2 %.2e max %.2e" % (dtype, nt, ny, rough, e2, em))
+    # FP32: a flux difference over dtau of rounded fluxes (cancellation on smooth data)
+    bar = 1e-12 if dtype == "f64" else max(2e-5, 2.5e-8 * nt)
+    assert e2 < bar and em < 5 * bar
+
+
+CASES = [
+    # nt, ny, steps, sched, scheme, reg, y_threads
+    (256, 64, 8, False, 0, False, None),
+    (512, 128, 6, True, 0, False, None),
+    (256, 64, 8, False, 1, False, None),
+    (256, 64, 8, True, 0, True, None),
+    (128, 256, 6, False, 1, True, None),
+    (1024, 1024, 3, True, 0, False, 512),     # full-tile y-pass
+    (1024, 1024, 3, False, 0, True, 1024),    # full-tile, regularised (FP32 only size)
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES, ids=["%dx%d-%d%s%s%s" % (c[0], c[1], c[2], "s" if c[3] else "",
+                                                                  "e" if c[4] else "", "r" if c[5] else "")
+                                             for c in CASES])
+def test_transport_march_matches_oracle(torch_cuda, orc, dtype, case):
+    nt, ny, ns, sched, scheme, reg, yt = case
+    if yt == 1024 and dtype == "f64":
+        yt = 512
+    p = medium_case(nt, ny, ns, sched=sched, scheme=scheme, reg=EPS[dtype] if reg else 0.0)
+    ref = orc.run(p)
+    got = march(p, dtype, yt)
+    e2, em = rel_l2(got, ref), max_rel(got, ref)
+    print("transport march %s %s: rel l2 %.2e max %.2e" % (dtype, case, e2, em))
+    assert e2 < TOL[dtype] and em < TOL[dtype], (e2, em)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_paper_set1_stand_in_matches_oracle(torch_cuda, orc, dtype):
+    """The paper's workload (Sec. 4 parameters, random medium, regularised
+    multiplier, its N-wave) on the 512 x 1024 stand-in grid of set 1, first
+    steps (h = 0.4)."""
+    p = I.paper_set(1, reg_eps=EPS[dtype], n_steps=6)
+    ref = orc.run(p)
+    got = march(p, dtype)
+    e2, em = rel_l2(got, ref), max_rel(got, ref)
+    print("paper set 1 stand-in %s, 6 steps: rel l2 %.2e max %.2e" % (dtype, e2, em))
+    assert e2 < TOL[dtype] and em < TOL[dtype], (e2, em)
