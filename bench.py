@@ -210,7 +210,54 @@ def side_measurements(args, value_fp32, ms_fp32):
     out["batched_c4_f32"] = {"solves": len(probs), "points": pts, "s_per_march": tb,
                              "value": pts * 500 / tb, "graph": True, "autotuned": plan.tuning()}
     plan.close()
+    del plan, u, u0
+    torch.cuda.empty_cache()
+    out["paper_sets_f32"] = paper_sets()
     return out
+
+
+# Table 2 of the paper, CUDA FP32 column (Titan V), seconds for the whole run of
+# each set on its own grid (N_theta = 7 * 2^k): context, not a target
+PAPER_CUDA_FP32_S = {1: 0.5564, 2: 3.788, 3: 28.31}
+
+
+def paper_sets():
+    """The paper's workload (full b with transport by the random medium,
+    regularised multiplier) on the power-of-two stand-in grids of sets 1-3,
+    each run for its N_sigma steps in FP32 with per-kernel events on every 8th
+    step; the paper's own times are on its larger 7 * 2^k grids."""
+    import torch
+    from paper_2103_06080_amd import inputs, kzk
+    res = {}
+    for k in (1, 2, 3):
+        p = inputs.paper_set(k)
+        plan = kzk.Plan(p, dtype="f32")
+        u0 = plan.pack([p.u0])
+        u = u0.clone()
+        plan.step(u, 0, p.n_steps)
+        assert plan.poll() == 0
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(u, 0, p.n_steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        u.copy_(u0)
+        plan.profile(True, every=PROFILE_EVERY)
+        plan.step(u, 0, p.n_steps)
+        prof = plan.profile_read()
+        plan.profile(False)
+        assert plan.poll() == 0
+        ns, nrho, nth = inputs.PAPER_SETS[k]
+        res["set%d" % k] = {"grid": [p.n_tau, p.n_y], "steps": p.n_steps, "s": t,
+                            "value": p.points * p.n_steps / t,
+                            "kernels_avg_us": {kk: round(1e3 * v[0] / v[1], 1) for kk, v in prof.items()},
+                            "paper_grid": [nth, nrho], "paper_cuda_fp32_s": PAPER_CUDA_FP32_S[k],
+                            "paper_value": nth * nrho * ns / PAPER_CUDA_FP32_S[k]}
+        plan.close()
+        del plan, u, u0
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
