@@ -174,6 +174,28 @@ def side_measurements(args, value_fp32, ms_fp32):
     plan.close()
     del plan, u, u0
     torch.cuda.empty_cache()
+    # FP32 with the spectral state in FP64: the same march, its error on the
+    # stored oracle rows, and the error of the linear 2000-step march against
+    # its closed form (plain FP32 state and FP64 state)
+    plan = kzk.Plan(p, dtype="f32", state_fp64=True)
+    u0 = plan.pack([p.u0])
+    u = u0.clone()
+    plan.step(u, 0, p.n_steps)
+
+    def s64_march():
+        u.copy_(u0)
+        plan.step(u, 0, p.n_steps)
+    t = _time(s64_march, sync)
+    assert plan.poll() == 0
+    rows = sampled_march_error("c3", u.double().cpu().numpy().reshape(p.n_y, p.n_tau), p.n_steps)
+    plan.close()
+    del plan, u, u0
+    torch.cuda.empty_cache()
+    out["fp32_state64_c3"] = {"s_per_march": t, "value": p.points * p.n_steps / t,
+                              "slowdown_vs_fp32_state": t / (p.points * p.n_steps / value_fp32),
+                              "full_march_sampled_rows": rows,
+                              "linear_march_vs_closed_form": {"fp32_state": linear_march_error(False),
+                                                              "fp64_state": linear_march_error(True)}}
     # adjoint / forward on the adjoint workload (FP32 and FP64); its 8 / 16 MB
     # arrays fit the 256 MB Infinity Cache, so these rates are cache-assisted
     q = inputs.c5()
@@ -214,6 +236,34 @@ def side_measurements(args, value_fp32, ms_fp32):
     torch.cuda.empty_cache()
     out["paper_sets_f32"] = paper_sets()
     return out
+
+
+def linear_march_error(state_fp64):
+    """Relative l2 error of the FP32 2000-step 8192 x 4096 march with nl = 0
+    (the workload's D(x) schedule and absorption) against its closed form:
+    u0 = cos(k tau) exp(-y^2 / 2), u(x) = e^{-A k^2 x} Re[e^{i k tau} (1/sqrt(c))
+    exp(-y^2 / (2 c))], c = 1 - i (int D dx) / k."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2103_06080_amd import inputs, kzk
+    p = inputs.c3()
+    p.nl_node = np.zeros_like(p.nl_node)
+    tau, y = p.tau(), p.y()
+    k = 2 * math.pi * 3 / p.L_tau
+    p.u0 = np.cos(k * tau)[None, :] * np.exp(-y ** 2 / 2)[:, None]
+    plan = kzk.Plan(p, dtype="f32", state_fp64=state_fp64)
+    u = plan.pack([p.u0])
+    plan.step(u, 0, p.n_steps)
+    assert plan.poll() == 0
+    got = plan.unpack(u)[0]
+    plan.close()
+    del plan, u
+    torch.cuda.empty_cache()
+    c = 1 - 1j * float(p.h * p.D_step.sum()) / k
+    ref = math.exp(-p.A * k * k * p.h * p.n_steps) * np.real(
+        np.exp(1j * k * tau)[None, :] / np.sqrt(c) * np.exp(-y ** 2 / (2 * c))[:, None])
+    return rel_l2(got, ref)
 
 
 # Table 2 of the paper, CUDA FP32 column (Titan V), seconds for the whole run of

@@ -99,6 +99,14 @@ typedef struct {
     int32_t vel_modes;
     const double *vel_phi, *vel_theta;
     double vel_lambda, vel_sigma_u, vel_c0;
+    /* FP32 plans only (ignored in FP64): 1 keeps the spectral state U and the
+       stage value P in FP64 (the combine of the y-passes in FP64, with the
+       step's multipliers evaluated in FP64 in stage 1), everything else in
+       FP32.  Without it the FP32 state is rounded every step while changing by
+       about one unit of FP32 rounding per step (E is within a few rounding
+       units of 1 at small h), so the rounding error adds up coherently over a
+       march.  The same for every solve of a plan; not with reg_eps > 0. */
+    int32_t state_fp64;
 } kzk_params;
 
 /* Create a plan for n_inst independent solves (n_inst >= 1), params[i] for
@@ -123,8 +131,8 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * first_step and lam_dev = dL/du at step first_step + n_steps, write dL/du0
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
  * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
- * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0);
- * KZK_ERR_ARG otherwise. */
+ * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0,
+ * state_fp64 0 in FP32); KZK_ERR_ARG otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 

@@ -53,6 +53,7 @@ struct kzk_plan {
     // physical field and transverse part of b per stage, its tau-spectrum,
     // velocity tables at the nodes, and the work list of the transverse pass
     bool transport = false;
+    bool s64 = false;                     // FP32 plan whose spectral state U and stage value P are FP64
     void *dUph = nullptr, *dByp = nullptr, *dBys = nullptr;
     kzk::YwItem* dYw = nullptr;
     int n_yw_items = 0;
@@ -174,6 +175,8 @@ kzk_status check_params(const kzk_params& q) {
     if (q.scheme != 0 && q.scheme != 1) return KZK_ERR_ARG;
     if (!(q.reg_eps >= 0) || !std::isfinite(q.reg_eps)) return KZK_ERR_ARG;
     if (q.vel != 0 && q.vel != 1) return KZK_ERR_ARG;
+    if (q.state_fp64 != 0 && q.state_fp64 != 1) return KZK_ERR_ARG;
+    if (q.state_fp64 && q.dtype == KZK_F32 && q.reg_eps > 0) return KZK_ERR_ARG;
     if (q.vel == 1) {
         if (q.vel_modes < 1 || !q.vel_phi || !q.vel_theta || q.n_steps_max < 1 || q.n_steps_max > 65534)
             return KZK_ERR_ARG;
@@ -292,7 +295,7 @@ kzk_status layout(kzk_plan* p) {
     p->y_full = 1;
     for (const InstDesc& d : p->desc)
         if (d.W * d.n_y != 16 * p->y_threads || d.n_y < 512) p->y_full = 0;
-    p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->y_threads, p->y_full, p->device);
+    p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->s64, p->y_threads, p->y_full, p->device);
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->dTau, tau.data(), sizeof(TauItem) * tau.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -338,9 +341,9 @@ hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     const void* by = stage > 0 && p->transport ? p->dBys : nullptr;
     if (p->dtype == KZK_F32)
-        return kzk::launch_y<float>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
-                                    p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
-    return kzk::launch_y<double>(stage, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
+        return kzk::launch_y<float>(stage, p->s64, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid,
+                                    p->dC, p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+    return kzk::launch_y<double>(stage, 0, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
                                  p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
@@ -488,13 +491,14 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         kzk_status st = check_params(params[i]);
         if (st != KZK_OK) return st;
         if (params[i].dtype != params[0].dtype || params[i].scheme != params[0].scheme ||
-            params[i].vel != params[0].vel)
+            params[i].vel != params[0].vel || params[i].state_fp64 != params[0].state_fp64)
             return KZK_ERR_ARG;
     }
     kzk_plan* p = new (std::nothrow) kzk_plan();
     if (!p) return KZK_ERR_OOM;
     p->scheme = params[0].scheme;
     p->transport = params[0].vel == 1;
+    p->s64 = params[0].state_fp64 == 1 && params[0].dtype == KZK_F32;
     p->arena = arena;
     p->arena_cap = arena ? arena_cap : 0;
     p->n_inst = n_inst;
@@ -565,8 +569,9 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
 
     const size_t cz = 2 * p->esz;   // bytes per complex
     kzk_status st = KZK_OK;
+    const size_t czs = p->s64 ? 2 * sizeof(double) : cz;   // bytes per complex of the state and stage value
     if ((st = dev_alloc(p, &p->dC, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dB, so * cz)) != KZK_OK ||
-        (st = dev_alloc(p, &p->dP, so * cz)) != KZK_OK || (st = dev_alloc(p, &p->dU, so * cz)) != KZK_OK ||
+        (st = dev_alloc(p, &p->dP, so * czs)) != KZK_OK || (st = dev_alloc(p, &p->dU, so * czs)) != KZK_OK ||
         (st = dev_alloc(p, &p->dTab, 3 * to * cz)) != KZK_OK ||
         (st = dev_alloc(p, &p->dTw, (size_t)ntw * cz)) != KZK_OK ||
         (st = dev_alloc(p, (void**)&p->dDesc, sizeof(InstDesc) * n_inst)) != KZK_OK ||
@@ -990,7 +995,8 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
 extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
-    if (p->scheme != 0 || p->any_reg || p->transport) return KZK_ERR_ARG;   // ExpRK22, zeroed mean, Burgers b
+    // ExpRK22, zeroed mean, Burgers b, state in the working precision
+    if (p->scheme != 0 || p->any_reg || p->transport || p->s64) return KZK_ERR_ARG;
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

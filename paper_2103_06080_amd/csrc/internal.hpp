@@ -73,8 +73,9 @@ bool tau_threads_supported(int dtype_is_f64, int nt);
 // W n_y = 16 nt and n_y >= 512 (full tiles; progression addressing).
 // By: tau-spectrum of the transverse transport part of b (instances with
 // vel = 1; nullptr otherwise), added to sigma_m B before the y-transform.
+// s64: an FP32 plan whose spectral state U and stage value P are FP64.
 template <typename T>
-hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
+hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
                     int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                     const void* twst, int step, hipStream_t s);
 
@@ -92,7 +93,7 @@ hipError_t launch_velocity(const InstDesc* d_desc, int inst, const double* modes
                            int n_nodes, double* tab, double* amax, hipStream_t s);
 // blocks of the y-pass kernels (block size nt, full-tile variant or not)
 // resident at once on the device
-int y_resident_blocks(int dtype_is_f64, int nt, int full, int device);
+int y_resident_blocks(int dtype_is_f64, int s64, int nt, int full, int device);
 
 template <typename T>
 hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_tiles, void* tabs, int step,

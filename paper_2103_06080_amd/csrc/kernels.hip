@@ -20,6 +20,7 @@
 #include "internal.hpp"
 
 #include <float.h>
+#include <type_traits>
 
 namespace kzk {
 
@@ -53,6 +54,8 @@ template <> __device__ __forceinline__ double rcp<double>(double x) {
 }
 
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+// complex value in another precision
+template <typename S, typename T> __device__ __forceinline__ cpx<S> cvs(cpx<T> a) { return cpx<S>{(S)a.x, (S)a.y}; }
 // maximum that propagates NaN (IEEE 754-2019 maximum; v_maximum3_f32 in FP32)
 template <typename T> __device__ __forceinline__ T nmax(T a, T b) { return __builtin_elementwise_maximum(a, b); }
 
@@ -935,13 +938,21 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // at LDS slot c (P + 32) + (c R mod 32) (P = padded n_y, R = 64/W rows of a
 // column per wave), so that the W row runs of one wave access cover the LDS
 // banks evenly instead of starting on the same bank.
-template <typename T, int NT, int STAGE, bool FULL>
+//
+// S: precision of the spectral state U and the stage value P (T, or double
+// in FP32 plans that keep their state in FP64: the combine then runs in FP64
+// with the step's multipliers evaluated in FP64, and only the inputs of the
+// inverse y-transform are rounded to T).
+template <typename T, int NT, int STAGE, bool FULL, typename S = T>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
-        const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
+        const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<S>* __restrict__ P, cpx<S>* __restrict__ U,
         cpx<T>* __restrict__ tabs, const cpx<T>* __restrict__ twst, int step) {
     __shared__ alignas(32) cpx<T> lds[padded(NT * 16) + (FULL ? NT : 0)];
     constexpr unsigned E = sizeof(cpx<T>);
+    // byte offsets of tile elements in the state arrays are ES times those in the others
+    constexpr unsigned ES = sizeof(cpx<S>) / sizeof(cpx<T>);
+    constexpr bool S64 = !std::is_same<S, T>::value;
     const int tid = threadIdx.x;
     // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...
     const cpx<T>* src = STAGE == 0 ? C : B;
@@ -963,8 +974,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     const long long to = d.off_state + (long long)m0 * Ny;
     const cpx<T>* Bt = B + to;
     cpx<T>* Ct = C + to;
-    cpx<T>* Pt = P + to;
-    cpx<T>* Ut = U + to;
+    cpx<S>* Pt = P + to;
+    cpx<S>* Ut = U + to;
     const cpx<T>* tE = tabs + d.off_tab + (long long)m0 * Nh;
     const cpx<T>* tP1 = tE + d.tab_stride;
     cpx<T>* tP2 = tabs + d.off_tab + (long long)m0 * Nh + 2 * d.tab_stride;
@@ -974,7 +985,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // x-dependent D: stage 1 computes the multipliers of this step (FP64)
     // instead of reading tables rebuilt every step, and stores h Phi2 / n_y
     // into its table for stage 2
-    const bool otf = STAGE == 1 && d.D_step != nullptr;
+    // (always, with an FP64 state: the stored tables are in T)
+    const bool otf = STAGE == 1 && (S64 || d.D_step != nullptr);
     // FULL geometry (unused otherwise)
     const int c = tid & (W - 1), j0 = tid >> lw;
     const int dq = Ny >> 4, sq = dq + (dq >> 4);
@@ -1030,12 +1042,13 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const auto rc = buf_rsrc(Ct), ru = buf_rsrc(Ut);
             #pragma unroll
             for (int q = 0; q < 16; ++q)
-                buf_st<T>(ru, tid * E, q * NT * E, keep_c ? lds[s0 + q * sq] : buf_ld<T>(rc, tid * E, q * NT * E));
+                buf_st<S>(ru, ES * tid * E, ES * q * NT * E,
+                          cvs<S>(keep_c ? lds[s0 + q * sq] : buf_ld<T>(rc, tid * E, q * NT * E)));
         } else {
             #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int e = tid + q * NT;
-                if (e < ne) Ut[e] = (col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)];
+                if (e < ne) Ut[e] = cvs<S>((col0 && (e & (W - 1)) == 0) ? Ct[e] : lds[KZK_LI(e)]);
             }
         }
         __syncthreads();
@@ -1066,39 +1079,39 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             // one item at a time (the FP64 multiplier code needs the registers);
             // the U loads of the next item are in flight during this item's
             // multipliers.  Column 0 of the first tile is handled pointwise below.
-            cpx<T> u0 = buf_ld<T>(rU, v0, 0), u1 = buf_ld<T>(rU, vm0, 0);
+            cpx<S> u0 = buf_ld<S>(rU, ES * v0, 0), u1 = buf_ld<S>(rU, ES * vm0, 0);
             #pragma unroll
             for (int q = 0; q < QH; ++q) {
-                cpx<T> x0 = u0, x1 = u1;
+                cpx<S> x0 = u0, x1 = u1;
                 if (q + 1 < QH) {
-                    x0 = buf_ld<T>(rU, vself(q + 1), (q + 1) * NT * E);
-                    if (q + 1 < 8) x1 = buf_ld<T>(rU, vpart(q + 1), spart(q + 1));
+                    x0 = buf_ld<S>(rU, ES * vself(q + 1), ES * (q + 1) * NT * E);
+                    if (q + 1 < 8) x1 = buf_ld<S>(rU, ES * vpart(q + 1), ES * spart(q + 1));
                 }
                 if (q < 8 || first) {
                     const int n = j0 + q * dq;
                     const bool two = q > 0 ? q < 8 : !first;
-                    cpx<T> E0 = {(T)0, (T)0}, P1 = E0, P2 = E0;
+                    cpx<S> E0 = {(S)0, (S)0}, P1 = E0, P2 = E0;
                     if (m0 + c > 0) {
-                        mode_multipliers<T>(d, m0 + c, n, step, E0, P1, P2);
+                        mode_multipliers<S>(d, m0 + c, n, step, E0, P1, P2);
                     } else if (n == 0) {
-                        T e, p1, p2;
-                        nyquist_multipliers<T>(d, e, p1, p2);
-                        P2 = cpx<T>{p2, (T)0};
+                        S e, p1, p2;
+                        nyquist_multipliers<S>(d, e, p1, p2);
+                        P2 = cpx<S>{p2, (S)0};
                     }
-                    buf_st<T>(rP2, vself(q), q * NT * E, P2);
+                    buf_st<T>(rP2, vself(q), q * NT * E, cvs<T>(P2));
                     {
                         const int li = s0 + q * sq;
-                        const cpx<T> bh = cmul(sg, lds[li]);
-                        const cpx<T> EU = cmul(E0, u0);
-                        if (keep_c) buf_st<T>(rP, vself(q), q * NT * E, EU + cmul(P1 - P2, bh));
-                        lds[li] = EU + cmul(P1, bh);
+                        const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
+                        const cpx<S> EU = cmul(E0, u0);
+                        if (keep_c) buf_st<S>(rP, ES * vself(q), ES * q * NT * E, EU + cmul(P1 - P2, bh));
+                        lds[li] = cvs<T>(EU + cmul(P1, bh));
                     }
                     if (two) {
                         const int li = s1 - q * sq;
-                        const cpx<T> bh = cmul(sg, lds[li]);
-                        const cpx<T> EU = cmul(E0, u1);
-                        if (keep_c) buf_st<T>(rP, vpart(q), spart(q), EU + cmul(P1 - P2, bh));
-                        lds[li] = EU + cmul(P1, bh);
+                        const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
+                        const cpx<S> EU = cmul(E0, u1);
+                        if (keep_c) buf_st<S>(rP, ES * vpart(q), ES * spart(q), EU + cmul(P1 - P2, bh));
+                        lds[li] = cvs<T>(EU + cmul(P1, bh));
                     }
                 }
                 u0 = x0;
@@ -1111,7 +1124,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             constexpr int QB = 3;
             #pragma unroll
             for (int q0 = 0; q0 < QH; q0 += QB) {
-                cpx<T> tb[QB][3], ua[QB][2];
+                cpx<T> tb[QB][3];
+                cpx<S> ua[QB][2];
                 #pragma unroll
                 for (int q = 0; q < QB; ++q) {
                     const int qq = q0 + q;
@@ -1120,12 +1134,12 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                         tb[q][0] = buf_ld<T>(rE, vs, ss);
                         tb[q][1] = buf_ld<T>(rP1, vs, ss);
                         tb[q][2] = buf_ld<T>(rP2, vs, ss);
-                        ua[q][0] = buf_ld<T>(rU, vs, ss);
-                        ua[q][1] = qq < 8 ? buf_ld<T>(rU, vpart(qq), spart(qq)) : ua[q][0];
+                        ua[q][0] = buf_ld<S>(rU, ES * vs, ES * ss);
+                        ua[q][1] = qq < 8 ? buf_ld<S>(rU, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
                     } else {
                         tb[q][2] = buf_ld<T>(rP2, vs, ss);
-                        ua[q][0] = buf_ld<T>(rP, vs, ss);
-                        ua[q][1] = qq < 8 ? buf_ld<T>(rP, vpart(qq), spart(qq)) : ua[q][0];
+                        ua[q][0] = buf_ld<S>(rP, ES * vs, ES * ss);
+                        ua[q][1] = qq < 8 ? buf_ld<S>(rP, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
                     }
                 }
                 #pragma unroll
@@ -1139,15 +1153,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                         const int li = pass ? s1 - qq * sq : s0 + qq * sq;
                         const unsigned vv = pass ? vpart(qq) : vself(qq);
                         const unsigned ss = pass ? spart(qq) : (unsigned)qq * NT * E;
-                        const cpx<T> bh = cmul(sg, lds[li]);
+                        const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                         if (STAGE == 1) {
-                            const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
-                            if (keep_c) buf_st<T>(rP, vv, ss, EU + cmul(tb[q][1] - tb[q][2], bh));
-                            lds[li] = EU + cmul(tb[q][1], bh);
+                            const cpx<S> EU = cmul(cvs<S>(tb[q][0]), ua[q][pass]);
+                            if (keep_c) buf_st<S>(rP, ES * vv, ES * ss, EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh));
+                            lds[li] = cvs<T>(EU + cmul(cvs<S>(tb[q][1]), bh));
                         } else {
-                            const cpx<T> un = ua[q][pass] + cmul(tb[q][2], bh);
-                            if (keep_c) buf_st<T>(rU, vv, ss, (T)Ny * un);
-                            lds[li] = un;
+                            const cpx<S> un = ua[q][pass] + cmul(cvs<S>(tb[q][2]), bh);
+                            if (keep_c) buf_st<S>(rU, ES * vv, ES * ss, (S)Ny * un);
+                            lds[li] = cvs<T>(un);
                         }
                     }
                 }
@@ -1159,7 +1173,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         // multipliers.  Column 0 of the first tile is handled pointwise below
         // (its combine values are never stored); its table slots hold the
         // tau-Nyquist scalars (n = 0) and zeros, as the tables kernel's.
-        cpx<T> u0, u1;
+        cpx<S> u0, u1;
         {
             const int h = min(tid, nh - 1);
             const int n = h >> lw, cc = h & (W - 1);
@@ -1169,7 +1183,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         }
         #pragma unroll
         for (int q = 0; q < QH; ++q) {
-            cpx<T> x0 = u0, x1 = u1;
+            cpx<S> x0 = u0, x1 = u1;
             if (q + 1 < QH) {
                 const int hn = min(tid + (q + 1) * NT, nh - 1);
                 const int n = hn >> lw, cc = hn & (W - 1);
@@ -1182,24 +1196,24 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 const int n = h >> lw, cc = h & (W - 1);
                 const bool keep_col = !(col0 && cc == 0);
                 const bool two = !(n == 0 || 2 * n == Ny);
-                cpx<T> E = {(T)0, (T)0}, P1 = E, P2 = E;
+                cpx<S> E = {(S)0, (S)0}, P1 = E, P2 = E;
                 if (m0 + cc > 0) {
-                    mode_multipliers<T>(d, m0 + cc, n, step, E, P1, P2);
+                    mode_multipliers<S>(d, m0 + cc, n, step, E, P1, P2);
                 } else if (n == 0) {
-                    T e, p1, p2;
-                    nyquist_multipliers<T>(d, e, p1, p2);
-                    P2 = cpx<T>{p2, (T)0};
+                    S e, p1, p2;
+                    nyquist_multipliers<S>(d, e, p1, p2);
+                    P2 = cpx<S>{p2, (S)0};
                 }
-                tP2[h] = P2;
+                tP2[h] = cvs<T>(P2);
                 #pragma unroll
                 for (int pass = 0; pass < 2; ++pass) {
                     if (pass == 1 && !two) break;
                     const int j = pass ? Ny - n : n;
                     const int e = j * W + cc, li = padi(cc * Ny + j);
-                    const cpx<T> bh = cmul(sg, lds[li]);
-                    const cpx<T> EU = cmul(E, pass ? u1 : u0);
+                    const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
+                    const cpx<S> EU = cmul(E, pass ? u1 : u0);
                     if (keep_col) Pt[e] = EU + cmul(P1 - P2, bh);
-                    lds[li] = EU + cmul(P1, bh);
+                    lds[li] = cvs<T>(EU + cmul(P1, bh));
                 }
             }
             u0 = x0;
@@ -1208,7 +1222,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     } else {
     #pragma unroll
     for (int q0 = 0; q0 < QH; q0 += 3) {
-        cpx<T> tb[3][3], ua[3][2];
+        cpx<T> tb[3][3];
+        cpx<S> ua[3][2];
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int h = min(tid + (q0 + q) * NT, nh - 1);   // clamped: loads without a branch
@@ -1239,17 +1254,17 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 if (pass == 1 && !two) break;
                 const int j = pass ? Ny - n : n;
                 const int e = j * W + cc, li = padi(cc * Ny + j);
-                const cpx<T> bh = cmul(sg, lds[li]);
+                const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                 if (STAGE == 1) {
-                    const cpx<T> EU = cmul(tb[q][0], ua[q][pass]);
-                    if (keep_col) Pt[e] = EU + cmul(tb[q][1] - tb[q][2], bh);
-                    lds[li] = EU + cmul(tb[q][1], bh);
+                    const cpx<S> EU = cmul(cvs<S>(tb[q][0]), ua[q][pass]);
+                    if (keep_col) Pt[e] = EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh);
+                    lds[li] = cvs<T>(EU + cmul(cvs<S>(tb[q][1]), bh));
                 } else {
                     // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
                     // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
-                    const cpx<T> un = ua[q][pass] + cmul(tb[q][2], bh);
-                    if (keep_col) Ut[e] = (T)Ny * un;
-                    lds[li] = un;
+                    const cpx<S> un = ua[q][pass] + cmul(cvs<S>(tb[q][2]), bh);
+                    if (keep_col) Ut[e] = (S)Ny * un;
+                    lds[li] = cvs<T>(un);
                 }
             }
         }
@@ -1274,9 +1289,9 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
 #undef KZK_LI
     if (col0) {
         // DC (.x) is invariant; the tau-Nyquist (.y) multipliers are ky-independent scalars
-        T EN, P1N, P2N;
+        S EN, P1N, P2N;
         if (otf) {
-            nyquist_multipliers<T>(d, EN, P1N, P2N);
+            nyquist_multipliers<S>(d, EN, P1N, P2N);
         } else {
             EN = tE[0].x;
             P1N = tP1[0].x;
@@ -1287,15 +1302,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             const long long o = (long long)y * W;
             // the mean mode (.x) is left to the DC path: zeroed F(b)(0, .), or
             // the mean-column kernel of the regularised multiplier
-            const cpx<T> b = {(T)0, sN * Bt[o].y + (tr ? By[to + o].y : (T)0)};
+            const S by = (S)(sN * Bt[o].y + (tr ? By[to + o].y : (T)0));
             if (STAGE == 1) {
-                const cpx<T> cr = Ut[o];
-                Ct[o] = cpx<T>{cr.x, EN * cr.y + P1N * b.y};
-                Pt[o] = cpx<T>{cr.x, EN * cr.y + (P1N - P2N) * b.y};
+                const cpx<S> cr = Ut[o];
+                Ct[o] = cvs<T>(cpx<S>{cr.x, EN * cr.y + P1N * by});
+                Pt[o] = cpx<S>{cr.x, EN * cr.y + (P1N - P2N) * by};
             } else {
-                const cpx<T> p = Pt[o];
-                const cpx<T> un = cpx<T>{p.x, p.y + P2N * b.y};
-                Ct[o] = un;
+                const cpx<S> p = Pt[o];
+                const cpx<S> un = cpx<S>{p.x, p.y + P2N * by};
+                Ct[o] = cvs<T>(un);
                 Ut[o] = un;
             }
         }
@@ -1729,40 +1744,54 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NT, bool FULL>
-static hipError_t launch_y_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                              void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
-                              int step, hipStream_t s) {
+template <typename T, int NT, bool FULL, typename S>
+static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
+                               void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
+                               int step, hipStream_t s) {
     dim3 g(max_blocks > 0 && max_blocks < n_items ? max_blocks : n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
     const cpx<T>* by = static_cast<const cpx<T>*>(By);
-    cpx<T>* p = static_cast<cpx<T>*>(P);
-    cpx<T>* u = static_cast<cpx<T>*>(U);
+    cpx<S>* p = static_cast<cpx<S>*>(P);
+    cpx<S>* u = static_cast<cpx<S>*>(U);
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
-                           step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+                           ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
-                           step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+                           ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb, ws,
-                           step);
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+                           ws, step);
     return hipGetLastError();
 }
 
-template <typename T, int NT>
+// s64: FP32 plan with the state in FP64
+template <typename T, int NT, bool FULL>
+static hipError_t launch_y_nt(int stage, int s64, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                              int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+                              const void* twst, int step, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (s64)
+            return launch_y_nts<T, NT, FULL, double>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                                     tabs, twst, step, s);
+    }
+    return launch_y_nts<T, NT, FULL, T>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst, step,
+                                        s);
+}
+
+template <typename T, int NT, typename S>
 static int y_resident_nt(int device, bool full) {
     int ncu = 0, per = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
         return 0;
     int lo = 1 << 30;
-    const void* fns[2][3] = {{(const void*)y_kernel<T, NT, 0, false>, (const void*)y_kernel<T, NT, 1, false>,
-                              (const void*)y_kernel<T, NT, 2, false>},
-                             {(const void*)y_kernel<T, NT, 0, true>, (const void*)y_kernel<T, NT, 1, true>,
-                              (const void*)y_kernel<T, NT, 2, true>}};
+    const void* fns[2][3] = {{(const void*)y_kernel<T, NT, 0, false, S>, (const void*)y_kernel<T, NT, 1, false, S>,
+                              (const void*)y_kernel<T, NT, 2, false, S>},
+                             {(const void*)y_kernel<T, NT, 0, true, S>, (const void*)y_kernel<T, NT, 1, true, S>,
+                              (const void*)y_kernel<T, NT, 2, true, S>}};
     for (const void* f : fns[full ? 1 : 0]) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, NT, 0) != hipSuccess || per <= 0) return 0;
         lo = per < lo ? per : lo;
@@ -1770,11 +1799,19 @@ static int y_resident_nt(int device, bool full) {
     return ncu * lo;
 }
 
-int y_resident_blocks(int is_f64, int nt, int full, int device) {
+int y_resident_blocks(int is_f64, int s64, int nt, int full, int device) {
+    if (is_f64) {
+        switch (nt) {
+        case 256: return y_resident_nt<double, 256, double>(device, full);
+        case 512: return y_resident_nt<double, 512, double>(device, full);
+        default: return 0;
+        }
+    }
     switch (nt) {
-    case 256: return is_f64 ? y_resident_nt<double, 256>(device, full) : y_resident_nt<float, 256>(device, full);
-    case 512: return is_f64 ? y_resident_nt<double, 512>(device, full) : y_resident_nt<float, 512>(device, full);
-    case 1024: return is_f64 ? 0 : y_resident_nt<float, 1024>(device, full);
+    case 256: return s64 ? y_resident_nt<float, 256, double>(device, full) : y_resident_nt<float, 256, float>(device, full);
+    case 512: return s64 ? y_resident_nt<float, 512, double>(device, full) : y_resident_nt<float, 512, float>(device, full);
+    case 1024:
+        return s64 ? y_resident_nt<float, 1024, double>(device, full) : y_resident_nt<float, 1024, float>(device, full);
     default: return 0;
     }
 }
@@ -1785,34 +1822,34 @@ bool y_threads_supported(int is_f64, int nt) {
 }
 
 template <typename T, bool FULL>
-static hipError_t launch_y_full(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
+static hipError_t launch_y_full(int stage, int s64, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
                                 int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                                 const void* twst, int step, hipStream_t s) {
     switch (nt) {
     case 256:
-        return launch_y_nt<T, 256, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+        return launch_y_nt<T, 256, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                          step, s);
     case 512:
-        return launch_y_nt<T, 512, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+        return launch_y_nt<T, 512, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                          step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024, FULL>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                              step, s);
+            return launch_y_nt<T, 1024, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+                                              twst, step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_y(int stage, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
+hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
                     int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                     const void* twst, int step, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    return full ? launch_y_full<T, true>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                         step, s)
-                : launch_y_full<T, false>(stage, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                          step, s);
+    return full ? launch_y_full<T, true>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+                                         twst, step, s)
+                : launch_y_full<T, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+                                          twst, step, s);
 }
 
 // b^ = sigma F^ in place on one instance's tiled tau-spectrum (element e of
@@ -1960,8 +1997,8 @@ void stage_twiddles(double* out) {
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
                                       void*, const void*, const void*, int, int, int, int, unsigned*, hipStream_t);  \
-    template hipError_t launch_y<T>(int, int, int, const InstDesc*, const YItem*, int, int, void*, const void*,     \
-                                    const void*, void*, void*, void*, const void*, int, hipStream_t);                \
+    template hipError_t launch_y<T>(int, int, int, int, const InstDesc*, const YItem*, int, int, void*,             \
+                                    const void*, const void*, void*, void*, void*, const void*, int, hipStream_t);   \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, const void*, hipStream_t);       \
     template hipError_t launch_dc<T>(int, const InstDesc*, int, void*, void*, void*, const void*, const void*, int,   \

@@ -56,6 +56,7 @@ class Params(ctypes.Structure):
         ("vel_lambda", ctypes.c_double),
         ("vel_sigma_u", ctypes.c_double),
         ("vel_c0", ctypes.c_double),
+        ("state_fp64", ctypes.c_int32),
     ]
 
 
@@ -119,7 +120,7 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None) -> Params:
+def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None, state_fp64: bool = False) -> Params:
     """kzk_params from an inputs.Problem (schedules only for x-dependent coefficients)."""
     null = ctypes.POINTER(ctypes.c_double)()
     D_ptr, nl_ptr, nmax = null, null, 0
@@ -155,7 +156,7 @@ def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None
                   int(getattr(p, "scheme", 0)), float(getattr(p, "reg_eps", 0.0)),
                   vel, int(getattr(p, "vel_modes", 0)), vphi, vtheta,
                   float(getattr(p, "vel_lambda", 0.0)), float(getattr(p, "vel_sigma_u", 0.0)),
-                  float(getattr(p, "vel_c0", 0.0)))
+                  float(getattr(p, "vel_c0", 0.0)), 1 if state_fp64 else 0)
 
 
 def step_noalloc(problems, u, first: int = 0, n_steps: int = 1, dtype: str = "f64", stream=None,
@@ -176,7 +177,8 @@ class Plan:
     """A kzk_plan for one or several solves (uneven grids allowed)."""
 
     def __init__(self, problems, dtype: str = "f64", stream=None, cfl_max: float = 1.0,
-                 y_threads: Optional[int] = None, graph: bool = False, tau_threads: Optional[int] = None):
+                 y_threads: Optional[int] = None, graph: bool = False, tau_threads: Optional[int] = None,
+                 state_fp64: bool = False):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -184,7 +186,7 @@ class Plan:
         torch = _torch()
         self.tdtype = torch.float32 if self.dtype == KZK_F32 else torch.float64
         keep: list = []
-        arr = (Params * len(problems))(*[make_params(p, self.dtype, cfl_max, keep) for p in problems])
+        arr = (Params * len(problems))(*[make_params(p, self.dtype, cfl_max, keep, state_fp64) for p in problems])
         h = ctypes.c_void_p()
         _check(lib().kzk_create(arr, len(problems), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)),
                "kzk_create")

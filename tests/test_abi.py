@@ -42,13 +42,14 @@ def _params(**kw):
     from paper_2103_06080_amd import kzk
     base = dict(n_tau=64, n_y=32, tau0=-4.0, L_tau=8.0, y0=-8.0, L_y=16.0, x0=0.0, h=1e-3, dtype=1,
                 D=0.05, A=0.0, nl=1.0, D_step=None, nl_node=None, n_steps_max=0, lf_scope=0,
-                weno_eps=1e-6, cfl_max=1.0, scheme=0, reg_eps=0.0, vel=0)
+                weno_eps=1e-6, cfl_max=1.0, scheme=0, reg_eps=0.0, vel=0, state_fp64=0)
     base.update(kw)
     null = ctypes.POINTER(ctypes.c_double)()
     return kzk.Params(base["n_tau"], base["n_y"], base["tau0"], base["L_tau"], base["y0"], base["L_y"],
                       base["x0"], base["h"], base["dtype"], base["D"], base["A"], base["nl"], null, null,
                       base["n_steps_max"], base["lf_scope"], base["weno_eps"], base["cfl_max"],
-                      base["scheme"], base["reg_eps"], base["vel"], 0, null, null, 0.0, 0.0, 0.0)
+                      base["scheme"], base["reg_eps"], base["vel"], 0, null, null, 0.0, 0.0, 0.0,
+                      base["state_fp64"])
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -56,7 +57,7 @@ def _params(**kw):
     (dict(h=0.0), 1), (dict(h=-1.0), 1), (dict(L_tau=0.0), 1), (dict(dtype=3), 1), (dict(A=-1.0), 1),
     (dict(weno_eps=0.0), 1), (dict(lf_scope=1), 1), (dict(cfl_max=-1.0), 1),
     (dict(scheme=2), 1), (dict(scheme=-1), 1), (dict(reg_eps=-1e-16), 1), (dict(reg_eps=float("nan")), 1),
-    (dict(vel=2), 1), (dict(vel=1), 1),
+    (dict(vel=2), 1), (dict(vel=1), 1), (dict(state_fp64=2), 1), (dict(state_fp64=1, dtype=0, reg_eps=1e-7), 1),
 ])
 def test_create_rejects_bad_parameters_before_device_work(kw, code):
     from paper_2103_06080_amd import kzk
