@@ -80,10 +80,56 @@ static void fft_core(cplx *a, int n, const cplx *w)
     }
 }
 
+/* Lengths that are not powers of two, n = 2^a m with m odd (the paper's
+   N_theta = 7 2^k): radix-2 decimation in time down to the odd length m,
+   whose transform is the direct sum of its definition.  s: n scratch values. */
+static void fft_mixed(cplx *a, int n, int sign, cplx *s)
+{
+    if (n % 2) {
+        for (int k = 0; k < n; ++k) {
+            cplx acc = 0;
+            for (int j = 0; j < n; ++j) {
+                double ang = sign * 2.0 * PI * (double)(((long)j * k) % n) / (double)n;
+                acc += a[j] * (cos(ang) + I * sin(ang));
+            }
+            s[k] = acc;
+        }
+        memcpy(a, s, sizeof(cplx) * (size_t)n);
+        return;
+    }
+    int h = n / 2;
+    for (int i = 0; i < h; ++i) {
+        s[i] = a[2 * i];
+        s[h + i] = a[2 * i + 1];
+    }
+    memcpy(a, s, sizeof(cplx) * (size_t)n);     /* a = [even samples | odd samples] */
+    fft_mixed(a, h, sign, s);
+    fft_mixed(a + h, h, sign, s);
+    for (int k = 0; k < h; ++k) {
+        double ang = sign * 2.0 * PI * (double)k / (double)n;
+        cplx t = (cos(ang) + I * sin(ang)) * a[h + k];
+        cplx e = a[k];
+        a[k] = e + t;
+        a[k + h] = e - t;
+    }
+}
+
+static int is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* one transform of length n: radix-2 with the twiddle table w (powers of two),
+   else the mixed-radix recursion with scratch s */
+static void fft_one(cplx *a, int n, int sign, const cplx *w, cplx *s)
+{
+    if (is_pow2(n)) fft_core(a, n, w);
+    else fft_mixed(a, n, sign, s);
+}
+
 void orc_fft(double *x, int n, int sign)
 {
     cplx *w = twiddles(n, sign);
-    fft_core((cplx *)x, n, w);
+    cplx *s = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    fft_one((cplx *)x, n, sign, w, s);
+    free(s);
     free(w);
 }
 
@@ -92,19 +138,26 @@ void orc_fft2(double *x, int ny, int nt, int sign)
     cplx *a = (cplx *)x;
     cplx *wt = twiddles(nt, sign), *wy = twiddles(ny, sign);
     /* along tau: rows */
-    #pragma omp parallel for schedule(static)
-    for (int j = 0; j < ny; ++j) fft_core(a + (size_t)j * nt, nt, wt);
+    #pragma omp parallel
+    {
+        cplx *s = (cplx *)malloc(sizeof(cplx) * (size_t)nt);
+        #pragma omp for schedule(static)
+        for (int j = 0; j < ny; ++j) fft_one(a + (size_t)j * nt, nt, sign, wt, s);
+        free(s);
+    }
     /* along y: columns, gathered into a contiguous buffer */
     #pragma omp parallel
     {
         cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+        cplx *s = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
         #pragma omp for schedule(static)
         for (int k = 0; k < nt; ++k) {
             for (int j = 0; j < ny; ++j) col[j] = a[(size_t)j * nt + k];
-            fft_core(col, ny, wy);
+            fft_one(col, ny, sign, wy, s);
             for (int j = 0; j < ny; ++j) a[(size_t)j * nt + k] = col[j];
         }
         free(col);
+        free(s);
     }
     free(wt);
     free(wy);

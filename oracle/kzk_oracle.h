@@ -29,7 +29,8 @@ extern "C" {
 #endif
 
 typedef struct {
-    int    nt, ny;          /* grid points along tau and y (powers of two)           */
+    int    nt, ny;          /* grid points along tau and y (even; powers of two, or
+                               2^a times an odd factor such as the paper's 7 2^k)     */
     double tau0, Lt;        /* tau box [tau0, tau0 + Lt)                             */
     double y0, Ly;          /* y box   [y0, y0 + Ly)                                 */
     double x0, h;           /* marching origin and step                              */
@@ -62,7 +63,8 @@ typedef struct {
     const double *vel_prof;
 } orc_cfg;
 
-/* In-place radix-2 complex FFT of length n (power of two) with unit stride.
+/* In-place complex FFT of length n with unit stride: radix-2 for powers of
+   two, radix-2 steps down to the odd factor (taken by its direct sum) else.
    sign = -1: X_k = sum_j x_j e^{-2 pi i jk/n}; sign = +1: the conjugate kernel.
    No normalisation in either direction. */
 void orc_fft(double *x_interleaved, int n, int sign);

@@ -11,6 +11,7 @@ import shutil
 
 import pytest
 
+import test_oracle_paper_grids as PG
 import test_oracle_pins as P
 import test_oracle_transport as TR
 import test_oracle_variants as V
@@ -101,6 +102,13 @@ MUTATIONS = [
      "amp[n] = sqrt(E) / c->vel_c0;", None, [TR.test_velocity_field_is_bounded_as_stated]),
     ("velocity: mode vector not normal to K", "double U1 = -amp[n] * sin(th), U2 = amp[n] * cos(th);",
      "double U1 = amp[n] * cos(th), U2 = amp[n] * sin(th);", None, [TR.test_velocity_field_is_divergence_free]),
+    ("mixed-radix FFT: odd-length sum with the wrong sign",
+     "double ang = sign * 2.0 * PI * (double)(((long)j * k) % n) / (double)n;",
+     "double ang = -sign * 2.0 * PI * (double)(((long)j * k) % n) / (double)n;", None,
+     [lambda o: PG.test_mixed_radix_fft_matches_direct_dft(o, 56, -1)]),
+    ("mixed-radix FFT: halves not recombined with twiddles",
+     "cplx t = (cos(ang) + I * sin(ang)) * a[h + k];", "cplx t = a[h + k];", None,
+     [lambda o: PG.test_mixed_radix_fft_matches_numpy(o, 448)]),
     ("adjoint: multiplier not conjugated", "w->W[i] = conj(M[i]) * V[i];", "w->W[i] = M[i] * V[i];", None,
      [lambda o: P.test_full_adjoint_matches_central_differences(o, 3)]),
 ]
