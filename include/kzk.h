@@ -56,7 +56,10 @@ typedef enum {
 typedef enum { KZK_F32 = 0, KZK_F64 = 1 } kzk_dtype;
 
 typedef struct {
-    int32_t n_tau, n_y;     /* powers of two: n_tau in [32, 8192], n_y in [16, 4096]      */
+    int32_t n_tau, n_y;     /* n_y a power of two in [16, 4096]; n_tau a power of two in
+                               [32, 8192], or 7 * 2^k in [224, 7168] (the grids of Sec. 4,
+                               N_theta = 7 * 2^k: a radix-7 stage in the tau-transform;
+                               then every solve of the plan has the same n_tau)          */
     double tau0, L_tau;     /* periodic tau box [tau0, tau0 + L_tau)                      */
     double y0, L_y;         /* periodic y box [y0, y0 + L_y)                              */
     double x0, h;           /* marching origin and step: x_n = x0 + n h (paper: Delta sigma) */
@@ -132,7 +135,7 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
  * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
  * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0,
- * state_fp64 0 in FP32); KZK_ERR_ARG otherwise. */
+ * state_fp64 0 in FP32) on power-of-two n_tau; KZK_ERR_ARG otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 
@@ -159,8 +162,8 @@ kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
 /* Select the tau-pass block size: 256 threads (one 8192-point line per
  * block), or 512 in FP32 only (two such lines, so the rows that share the
- * 128-byte lines of the column-tiled spectra belong to fewer blocks).
- * 0 restores the default (256). */
+ * 128-byte lines of the column-tiled spectra belong to fewer blocks);
+ * 256 only with n_tau = 7 * 2^k.  0 restores the default (256). */
 kzk_status kzk_set_tau_threads(kzk_plan *plan, int32_t threads);
 
 /* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is

@@ -22,6 +22,12 @@ namespace {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2i(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+// K with n_tau = 7 * 2^(K+1), 4 <= K <= 9 (M = n_tau/2 = 7 * 2^K, 112 .. 3584), else 0
+int gen_k(int n_tau) {
+    if (n_tau % 14 != 0 || !pow2(n_tau / 14)) return 0;
+    const int k = ilog2i(n_tau / 14);
+    return k >= 4 && k <= 9 ? k : 0;
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -45,6 +51,7 @@ struct kzk_plan {
     int y_threads = 0;
     int y_grid = 0;                       // persistent y-pass blocks (resident at once)
     int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
+    int gk = 0;                           // > 0: every instance has M = 7 * 2^gk (mixed-radix tau-pass)
     int y_full = 0;                       // every instance has W n_y = 16 y_threads and n_y >= 512 (full y tiles)
     bool any_D_sched = false;
     int scheme = 0;                       // 0: ExpRK22, 1: exponential Euler (every solve)
@@ -163,7 +170,7 @@ struct ProfScope {
 };
 
 kzk_status check_params(const kzk_params& q) {
-    if (!pow2(q.n_tau) || !pow2(q.n_y)) return KZK_ERR_SIZE;
+    if ((!pow2(q.n_tau) && !gen_k(q.n_tau)) || !pow2(q.n_y)) return KZK_ERR_SIZE;
     if (q.n_tau < 32 || q.n_tau > 8192 || q.n_y < 16 || q.n_y > 4096) return KZK_ERR_SIZE;
     if (!(q.L_tau > 0) || !(q.L_y > 0) || !(q.h > 0) || !std::isfinite(q.h)) return KZK_ERR_ARG;
     if (q.dtype != KZK_F32 && q.dtype != KZK_F64) return KZK_ERR_ARG;
@@ -274,11 +281,13 @@ kzk_status layout(kzk_plan* p) {
     std::vector<YItem> ys;
     for (int i = 0; i < p->n_inst; ++i) {
         InstDesc& d = p->desc[i];
-        int W = std::min(p->y_threads * 16 / d.n_y, d.M);
+        // column tiles of W modes, W a power of two dividing M (2^K for M = 7 * 2^K)
+        int W = std::min(p->y_threads * 16 / d.n_y, p->gk ? (1 << p->gk) : d.M);
         d.W = W;
         d.log2W = ilog2i(W);
-        d.rows_per_tau_block = p->tau_threads * 16 / d.M;
-        const int rows_adj = kzk::TAU_THREADS * 16 / d.M;
+        // lines of M/16 threads; with M = 7 * 2^K they sit in groups of 2^(K-1)
+        d.rows_per_tau_block = p->gk ? p->tau_threads >> (p->gk - 1) : p->tau_threads * 16 / d.M;
+        const int rows_adj = p->gk ? kzk::TAU_THREADS >> (p->gk - 1) : kzk::TAU_THREADS * 16 / d.M;
         for (int r = 0; r < d.n_y; r += d.rows_per_tau_block) tau.push_back({i, r});
         for (int r = 0; r < d.n_y; r += rows_adj) tau_adj.push_back({i, r});
         for (int m = 0; m < d.M; m += W) ys.push_back({i, m});
@@ -289,7 +298,7 @@ kzk_status layout(kzk_plan* p) {
     p->n_tau_items = (int)tau.size();
     p->n_tau_adj_items = (int)tau_adj.size();
     p->n_y_items = (int)ys.size();
-    p->tau_prog = 1;
+    p->tau_prog = p->gk ? 0 : 1;
     for (const InstDesc& d : p->desc)
         if (d.M / 16 < d.W || d.M < 256) p->tau_prog = 0;
     p->y_full = 1;
@@ -329,10 +338,10 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
     if (p->dtype == KZK_F32)
         return kzk::launch_tau<float>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in,
                                       (float*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
-                                      p->tau_prog, p->dStatus, p->stream);
+                                      p->tau_prog, p->gk, p->dStatus, p->stream);
     return kzk::launch_tau<double>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in,
                                    (double*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
-                                   p->tau_prog, p->dStatus, p->stream);
+                                   p->tau_prog, p->gk, p->dStatus, p->stream);
 }
 
 // step: the ExpRK22 step, for instances with a D schedule (the y-pass
@@ -493,11 +502,15 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         if (params[i].dtype != params[0].dtype || params[i].scheme != params[0].scheme ||
             params[i].vel != params[0].vel || params[i].state_fp64 != params[0].state_fp64)
             return KZK_ERR_ARG;
+        // n_tau = 7 * 2^(K+1): one tau length for the whole plan
+        if ((gen_k(params[i].n_tau) || gen_k(params[0].n_tau)) && params[i].n_tau != params[0].n_tau)
+            return KZK_ERR_SIZE;
     }
     kzk_plan* p = new (std::nothrow) kzk_plan();
     if (!p) return KZK_ERR_OOM;
     p->scheme = params[0].scheme;
     p->transport = params[0].vel == 1;
+    p->gk = gen_k(params[0].n_tau);
     p->s64 = params[0].state_fp64 == 1 && params[0].dtype == KZK_F32;
     p->arena = arena;
     p->arena_cap = arena ? arena_cap : 0;
@@ -546,7 +559,7 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         uo += (size_t)q.n_tau * q.n_y;
         to += (size_t)d.M * d.Nh;
         ntw = std::max(ntw, std::max(q.n_tau, q.n_y));
-        const int rows256 = kzk::TAU_THREADS * 16 / d.M;
+        const int rows256 = p->gk ? kzk::TAU_THREADS >> (p->gk - 1) : kzk::TAU_THREADS * 16 / d.M;
         max_tau_items += (q.n_y + rows256 - 1) / rows256;
         max_y_items += d.M;   // W >= 1
         if (q.D_step) {
@@ -564,8 +577,11 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
     p->state_elems = so;
     p->tab_elems = to;
     for (int i = 0; i < n_inst; ++i) p->desc[i].tab_stride = (long long)to;
+    // the tau-pass twiddle table: e^{-2 pi i k / 2^log2_ntw}, or with
+    // n_tau = 7 * 2^(K+1) the table e^{-2 pi i k / n_tau} of that length
+    if (p->gk) ntw = params[0].n_tau;
     p->ntw = ntw;
-    p->log2_ntw = ilog2i(ntw);
+    p->log2_ntw = p->gk ? 0 : ilog2i(ntw);
 
     const size_t cz = 2 * p->esz;   // bytes per complex
     kzk_status st = KZK_OK;
@@ -639,6 +655,7 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         }
     }
     // twiddles exp(-2 pi i k / ntw) in FP64, stored in the working precision
+    // (ntw = 2^log2_ntw, or n_tau = 7 * 2^(K+1))
     {
         std::vector<double> tw(2 * (size_t)ntw);
         for (int k = 0; k < ntw; ++k) {
@@ -709,6 +726,7 @@ kzk_status kzk_set_tau_threads(kzk_plan* p, int32_t threads) {
     if (!p) return KZK_ERR_ARG;
     if (threads == 0) threads = default_tau_threads(p);
     if (!kzk::tau_threads_supported(p->dtype == KZK_F64, threads)) return KZK_ERR_ARG;
+    if (p->gk && threads != kzk::TAU_THREADS) return KZK_ERR_ARG;   // lengths 7 * 2^K: one block size
     if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
     drop_graph(p);
     p->tau_threads = threads;
@@ -944,10 +962,13 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
     const char* cache = std::getenv("KZK_TUNE_CACHE");
     const std::string key = tune_key(p);
     kzk_status st = KZK_OK;
+    // tau-pass block sizes this plan can take (one with n_tau = 7 * 2^(K+1))
+    auto tau_ok = [&](int t) {
+        return kzk::tau_threads_supported(p->dtype == KZK_F64, t) && (!p->gk || t == kzk::TAU_THREADS);
+    };
     if (cache && *cache) {
         int yt = 0, tt = 0;
-        if (tune_lookup(cache, key, &yt, &tt) && kzk::y_threads_supported(p->dtype == KZK_F64, yt) &&
-            kzk::tau_threads_supported(p->dtype == KZK_F64, tt)) {
+        if (tune_lookup(cache, key, &yt, &tt) && kzk::y_threads_supported(p->dtype == KZK_F64, yt) && tau_ok(tt)) {
             if ((st = kzk_set_y_threads(p, yt)) != KZK_OK || (st = kzk_set_tau_threads(p, tt)) != KZK_OK)
                 return -(int32_t)st;
             return yt;
@@ -965,7 +986,7 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
         if (!kzk::y_threads_supported(p->dtype == KZK_F64, c)) continue;
         if ((st = kzk_set_y_threads(p, c)) != KZK_OK) break;
         for (int t : tcands) {
-            if (!kzk::tau_threads_supported(p->dtype == KZK_F64, t)) continue;
+            if (!tau_ok(t)) continue;
             if ((st = kzk_set_tau_threads(p, t)) != KZK_OK) break;
             // one untimed step to warm up, then n_trial timed steps, on the plan's own state
             if ((st = enqueue_forward(p, u)) != KZK_OK) break;
@@ -996,7 +1017,7 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
     // ExpRK22, zeroed mean, Burgers b, state in the working precision
-    if (p->scheme != 0 || p->any_reg || p->transport || p->s64) return KZK_ERR_ARG;
+    if (p->scheme != 0 || p->any_reg || p->transport || p->s64 || p->gk) return KZK_ERR_ARG;
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

@@ -100,6 +100,30 @@ template <typename T, int S> struct Dft<T, 16, S> {
     }
 };
 
+template <typename T, int S> struct Dft<T, 7, S> {
+    // With a_s = v_s + v_{7-s} and b_s = v_s - v_{7-s} (s = 1, 2, 3):
+    //   X_k     = v_0 + sum_s cos(2 pi s k / 7) a_s + S i sum_s sin(2 pi s k / 7) b_s,
+    //   X_{7-k} = the same with -S,  k = 1, 2, 3;  X_0 = v_0 + a_1 + a_2 + a_3.
+    // cos/sin(2 pi m / 7) for m = 1, 2, 3; the products s k reduce mod 7 to
+    // these with the signs below (sin(2 pi (7 - m) / 7) = -sin(2 pi m / 7)).
+    static __device__ __forceinline__ void run(cpx<T>* v) {
+        const T C1 = (T)0.62348980185873353053, C2 = (T)-0.22252093395631440429, C3 = (T)-0.90096886790241912624;
+        const T S1 = (T)0.78183148246802980871, S2 = (T)0.97492791218182360702, S3 = (T)0.43388373911755812048;
+        const cpx<T> a1 = v[1] + v[6], a2 = v[2] + v[5], a3 = v[3] + v[4];
+        const cpx<T> b1 = v[1] - v[6], b2 = v[2] - v[5], b3 = v[3] - v[4];
+        const cpx<T> x0 = v[0];
+        // k = 1: (C1, C2, C3), (S1, S2, S3); k = 2: (C2, C3, C1), (S2, -S3, -S1); k = 3: (C3, C1, C2), (S3, -S1, S2)
+        const cpx<T> c1 = x0 + C1 * a1 + C2 * a2 + C3 * a3, s1 = S1 * b1 + S2 * b2 + S3 * b3;
+        const cpx<T> c2 = x0 + C2 * a1 + C3 * a2 + C1 * a3, s2 = S2 * b1 - S3 * b2 - S1 * b3;
+        const cpx<T> c3 = x0 + C3 * a1 + C1 * a2 + C2 * a3, s3 = S3 * b1 - S1 * b2 + S2 * b3;
+        v[0] = x0 + a1 + a2 + a3;
+        const cpx<T> i1 = mul_si<S>(s1), i2 = mul_si<S>(s2), i3 = mul_si<S>(s3);
+        v[1] = c1 + i1; v[6] = c1 - i1;
+        v[2] = c2 + i2; v[5] = c2 - i2;
+        v[3] = c3 + i3; v[4] = c3 - i3;
+    }
+};
+
 // ---------------------------------------------------------------- twiddles
 // w(k) = exp(S 2 pi i k / Ntw) from tw[k] = exp(-2 pi i k / Ntw).
 template <int S, typename T> __device__ __forceinline__ cpx<T> twiddle(const cpx<T>* __restrict__ tw, int k) {
@@ -335,6 +359,78 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int n, int t, boo
     case 12: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 12>(buf, base, t, active, twst); break;
     default: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 13>(buf, base, t, active, twst); break;
     }
+}
+
+// ---------------------------------------------------------------- lengths 7 * 2^K
+// In-place length-M FFT, M = 7 * 2^K (4 <= K <= 9), of the sequence at
+// logical LDS positions base .. base+M-1, done by the threads t < M/16
+// where `active` (every thread of the block must call it).  Stockham
+// stages: radix 7 first (span 7, no twiddles), then radix-16 stages, then
+// one tail stage of radix 2, 4 or 8 for the rest of 2^K.  A stage with
+// M/R butterflies gives thread t the butterflies t + b M/16, b < ceil(16/R)
+// (the radix-7 stage: 16/7 per thread, so its third butterfly exists for
+// t < M/56 only).  Twiddles exp(S 2 pi i s k / (Ns R)) come from the table
+// tw[i] = exp(-2 pi i i / (2M)) at i = s k (2M / (Ns R)) (s k < Ns R, so
+// the index is in range for every thread, active or not).
+template <typename T, int S, int M, int NS, int R>
+__device__ __forceinline__ void gen_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ tw) {
+    constexpr int tpr = M / 16, NB = M / R, PER = (NB + tpr - 1) / tpr, TS = 2 * M / (NS * R);
+    constexpr bool RAGGED = NB % tpr != 0;
+    cpx<T> w[PER][R > 1 ? R - 1 : 1];
+    if constexpr (NS > 1) {
+        #pragma unroll
+        for (int b = 0; b < PER; ++b) {
+            const int k = (t + b * tpr) % NS;
+            #pragma unroll
+            for (int s = 1; s < R; ++s) w[b][s - 1] = twiddle<S>(tw, s * k * TS);
+        }
+    }
+    cpx<T> v[PER][R];
+    if (active) {
+        #pragma unroll
+        for (int b = 0; b < PER; ++b) {
+            const int j = t + b * tpr;
+            if (RAGGED && j >= NB) continue;
+            #pragma unroll
+            for (int s = 0; s < R; ++s) v[b][s] = buf[padi(base + j + s * NB)];
+        }
+    }
+    __syncthreads();
+    if (active) {
+        #pragma unroll
+        for (int b = 0; b < PER; ++b) {
+            const int j = t + b * tpr;
+            if (RAGGED && j >= NB) continue;
+            const int k = j % NS;
+            if constexpr (NS > 1) {
+                #pragma unroll
+                for (int s = 1; s < R; ++s) v[b][s] = cmul(v[b][s], w[b][s - 1]);
+            }
+            Dft<T, R, S>::run(v[b]);
+            const int o = base + (j - k) * R + k;
+            #pragma unroll
+            for (int s = 0; s < R; ++s) buf[padi(o + s * NS)] = v[b][s];
+        }
+    }
+    __syncthreads();
+}
+
+// the stages after the first: LR2 = log2 of the power of two still to do
+template <typename T, int S, int M, int NS, int LR2>
+__device__ __forceinline__ void gen_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ tw) {
+    if constexpr (LR2 > 0) {
+        constexpr int LR = LR2 >= 4 ? 4 : LR2;
+        gen_stage<T, S, M, NS, 1 << LR>(buf, base, t, active, tw);
+        gen_stages<T, S, M, NS * (1 << LR), LR2 - LR>(buf, base, t, active, tw);
+    }
+}
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void gen_fft(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ tw) {
+    static_assert(K >= 4 && K <= 9, "lengths 7 * 16 .. 7 * 512");
+    constexpr int M = 7 << K;
+    gen_stage<T, S, M, 1, 7>(buf, base, t, active, tw);
+    gen_stages<T, S, M, 7, K>(buf, base, t, active, tw);
 }
 
 }  // namespace kzk

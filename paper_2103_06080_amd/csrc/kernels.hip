@@ -410,6 +410,58 @@ __device__ __forceinline__ void r2c_post_prog(const cpx<T>* lds, int base, cpx<T
     }
 }
 
+// The two for M = 7 * 2^K (compile-time M): the same pairs k = t + q M/16
+// (q < 9, k <= M/2), with M - k taken mod M by a select and the twiddle
+// e^{-2 pi i k/N} read from the table tw[i] = e^{-2 pi i i/N} (N = 2M) at k.
+template <typename T, int M>
+__device__ __forceinline__ void c2r_pre_gen(const cpx<T>* __restrict__ X, SpecIdx ix, cpx<T>* lds, int base, int t,
+                                            const cpx<T>* __restrict__ tw, T inv_n) {
+    constexpr int tpr = M / 16, Q = 9;
+    cpx<T> xk[Q], xm[Q], wv[Q];
+    #pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = min(t + q * tpr, M / 2);
+        xk[q] = X[ix(k)];
+        xm[q] = X[ix(k == 0 ? 0 : M - k)];
+        wv[q] = tw[k];
+    }
+    #pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int k = t + q * tpr;
+        if (k > M / 2) continue;
+        if (k == 0) {
+            const cpx<T> s = xk[q];
+            lds[padi(base)] = cpx<T>{(s.x + s.y) * inv_n, (s.x - s.y) * inv_n};
+            continue;
+        }
+        cpx<T> zk, zm;
+        c2r_pair(xk[q], xm[q], wv[q], inv_n, zk, zm);
+        lds[padi(base + k)] = zk;
+        if (2 * k != M) lds[padi(base + M - k)] = zm;
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void r2c_post_gen(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int t,
+                                             const cpx<T>* __restrict__ tw) {
+    constexpr int tpr = M / 16;
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int k = t + q * tpr;
+        if (k > M / 2) continue;
+        const cpx<T> zk = lds[padi(base + k)];
+        const cpx<T> zm = lds[padi(base + (k == 0 ? 0 : M - k))];
+        cpx<T> a, b;
+        r2c_pair(zk, zm, tw[k], a, b);
+        if (k == 0) {
+            X[0] = cpx<T>{a.x, b.x};
+            continue;
+        }
+        X[ix(k)] = a;
+        if (2 * k != M) X[ix(M - k)] = b;
+    }
+}
+
 // MODE 0: u -> C (R2C).  MODE 1: C -> u (C2R).  MODE 2: C -> B, the
 // tau-spectrum of the WENO5 face fluxes F_{i+1/2} (the flux difference
 // b_i = -(F_{i+1/2} - F_{i-1/2}) / dtau is the Fourier multiplier
@@ -418,8 +470,11 @@ __device__ __forceinline__ void r2c_post_prog(const cpx<T>* lds, int base, cpx<T
 // PROG (mode 2 only): tiled spectra with tpr a multiple of the tile width and
 // of 16 in every instance (progression indexing of the pre/post-processing
 // pairs).  NTT: threads per block; a block holds NTT * 16 complex points, the
-// lines rows0 .. rows0 + NTT * 16 / M - 1.
-template <typename T, int MODE, bool PROG = false, int NTT = TAU_THREADS>
+// lines rows0 .. rows0 + NTT * 16 / M - 1.  GK > 0: every instance has
+// M = 7 * 2^GK (n_tau = 7 * 2^(GK+1)); its M/16 threads per line sit in an
+// aligned group of 2^(GK-1) (the rest of the group idle), so the block holds
+// NTT / 2^(GK-1) lines, and tw is the table e^{-2 pi i k / n_tau}, k < n_tau.
+template <typename T, int MODE, bool PROG = false, int NTT = TAU_THREADS, int GK = 0>
 __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ descs,
                                                   const TauItem* __restrict__ items,
                                                   const T* __restrict__ u_in, T* __restrict__ u_out,
@@ -433,11 +488,13 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
     // consecutive rows on one XCD: with column tiles, rows y..y+W-1 share cache lines
     const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
-    const int M = d.M, N = 2 * M;
+    static_assert(GK == 0 || (!PROG && NTT == TAU_THREADS), "lengths 7 * 2^K: plain indexing, 256 threads");
+    const int M = GK ? (7 << GK) : d.M, N = 2 * M;
     const int tpr = M >> 4;
-    const int r = threadIdx.x / tpr, t = threadIdx.x & (tpr - 1);
+    const int tpg = GK ? (1 << (GK - 1)) : tpr;   // threads of a line's group (a power of two)
+    const int r = threadIdx.x / tpg, t = threadIdx.x & (tpg - 1);
     const int row = it.row0 + r;
-    const bool active = (r < d.rows_per_tau_block) && (row < d.n_y);
+    const bool active = (GK == 0 || t < tpr) && (r < d.rows_per_tau_block) && (row < d.n_y);
     const int base = r * M;
     const int Nc = M >> 1;   // chunks of 4 reals per line
     const SpecIdx ix = spec_idx(d.log2W, d.n_y, tiled != 0);
@@ -457,22 +514,29 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
                 lds_quad_st(lds, base, t + q * tpr, v[q]);
             }
         }
-        bad = line_or(bad, tpr, redI);
+        bad = line_or(bad, tpg, redI);
         if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
         __syncthreads();
-        lds_fft<T, -1>(lds, base, M, t, active, twst);
-        if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+        if constexpr (GK > 0) {
+            gen_fft<T, -1, GK>(lds, base, t, active, tw);
+            if (active) r2c_post_gen<T, (7 << GK)>(lds, base, Bout + so, ix, t, tw);
+        } else {
+            lds_fft<T, -1>(lds, base, M, t, active, twst);
+            if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+        }
         return;
     }
 
     // inverse tau-transform of C~ into the line buffer
     if (active) {
-        if constexpr (PROG) c2r_pre_prog(Cin + d.off_state, (unsigned)row << d.log2W, ix, lds, base, M, t, tpr, tw,
-                                         log2_ntw, (T)1 / (T)N);
+        if constexpr (GK > 0) c2r_pre_gen<T, (7 << GK)>(Cin + so, ix, lds, base, t, tw, (T)1 / (T)N);
+        else if constexpr (PROG) c2r_pre_prog(Cin + d.off_state, (unsigned)row << d.log2W, ix, lds, base, M, t, tpr,
+                                              tw, log2_ntw, (T)1 / (T)N);
         else c2r_pre(Cin + so, ix, lds, base, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, base, M, t, active, twst);
+    if constexpr (GK > 0) gen_fft<T, 1, GK>(lds, base, t, active, tw);
+    else lds_fft<T, 1>(lds, base, M, t, active, twst);
 
     if (MODE == 1 || MODE == 3) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
@@ -494,7 +558,7 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
             for (int i = 0; i < 4; ++i) mx = nmax(mx, (T)fabs(v.v[i]));
         }
     }
-    mx = line_max(mx, tpr, redT);
+    mx = line_max(mx, tpg, redT);
     bool bad = !finite_val(mx);
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
     const T nlT = (T)nl;
@@ -516,8 +580,8 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
                 }
             }
         }
-        hi = line_max(hi, tpr, redT);
-        lo = line_max(lo, tpr, redT);
+        hi = line_max(hi, tpg, redT);
+        lo = line_max(lo, tpg, redT);
         alpha = tmax((T)fabs(nlT * hi - cpar), (T)fabs(nlT * -lo - cpar));
         bad = bad || !finite_val(alpha);
     }
@@ -541,7 +605,10 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
             T u[16];
             #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                const quad<T> v = lds_quad(lds, base, (2 * g - 1 + h) & (Nc - 1));
+                int c = 2 * g - 1 + h;   // chunk index mod Nc
+                if constexpr (GK > 0) c = c < 0 ? c + Nc : (c >= Nc ? c - Nc : c);
+                else c &= Nc - 1;
+                const quad<T> v = lds_quad(lds, base, c);
                 #pragma unroll
                 for (int i = 0; i < 4; ++i) u[4 * h + i] = v.v[i];
             }
@@ -559,11 +626,16 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
         }
     }
     __syncthreads();
-    lds_fft<T, -1>(lds, base, M, t, active, twst);
-    if (active) {
-        if constexpr (PROG) r2c_post_prog(lds, base, Bout + d.off_state, (unsigned)row << d.log2W, ix, M, t, tpr, tw,
-                                          log2_ntw);
-        else r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+    if constexpr (GK > 0) {
+        gen_fft<T, -1, GK>(lds, base, t, active, tw);
+        if (active) r2c_post_gen<T, (7 << GK)>(lds, base, Bout + so, ix, t, tw);
+    } else {
+        lds_fft<T, -1>(lds, base, M, t, active, twst);
+        if (active) {
+            if constexpr (PROG) r2c_post_prog(lds, base, Bout + d.off_state, (unsigned)row << d.log2W, ix, M, t, tpr,
+                                              tw, log2_ntw);
+            else r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
+        }
     }
 }
 
@@ -1726,13 +1798,43 @@ static hipError_t launch_tau_nt(int mode, const InstDesc* d_desc, const TauItem*
     return hipGetLastError();
 }
 
+template <typename T, int GK>
+static hipError_t launch_tau_gen(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
+                                 T* u_out, const void* Cin, void* Bout, const void* tw, int node, int tiled,
+                                 unsigned* status, hipStream_t s) {
+    dim3 g(n_items), b(TAU_THREADS);
+    const cpx<T>* ci = static_cast<const cpx<T>*>(Cin);
+    cpx<T>* bo = static_cast<cpx<T>*>(Bout);
+    const cpx<T>* w = static_cast<const cpx<T>*>(tw);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0, false, TAU_THREADS, GK>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, nullptr, 0, node, tiled, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1, false, TAU_THREADS, GK>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, nullptr, 0, node, tiled, status); break;
+    case 2: hipLaunchKernelGGL((tau_kernel<T, 2, false, TAU_THREADS, GK>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, nullptr, 0, node, tiled, status); break;
+    case 3: hipLaunchKernelGGL((tau_kernel<T, 3, false, TAU_THREADS, GK>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, nullptr, 0, node, tiled, status); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 bool tau_threads_supported(int is_f64, int nt) { return nt == TAU_THREADS || (nt == TAU_THREADS_WIDE && !is_f64); }
 
 template <typename T>
 hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, int prog, unsigned* status, hipStream_t s) {
+                      int node, int tiled, int prog, int gk, unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (gk != 0) {
+        if (nt != TAU_THREADS) return hipErrorInvalidValue;
+        switch (gk) {
+        case 4: return launch_tau_gen<T, 4>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        case 5: return launch_tau_gen<T, 5>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        case 6: return launch_tau_gen<T, 6>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        case 7: return launch_tau_gen<T, 7>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        case 8: return launch_tau_gen<T, 8>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        case 9: return launch_tau_gen<T, 9>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, node, tiled, status, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (nt == TAU_THREADS)
         return launch_tau_nt<T, TAU_THREADS>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, twst,
                                              log2_ntw, node, tiled, prog, status, s);
@@ -1996,7 +2098,8 @@ void stage_twiddles(double* out) {
 
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
-                                      void*, const void*, const void*, int, int, int, int, unsigned*, hipStream_t);  \
+                                      void*, const void*, const void*, int, int, int, int, int, unsigned*,          \
+                                      hipStream_t);                                                                 \
     template hipError_t launch_y<T>(int, int, int, int, const InstDesc*, const YItem*, int, int, void*,             \
                                     const void*, const void*, void*, void*, void*, const void*, int, hipStream_t);   \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \

@@ -264,22 +264,28 @@ def medium(seed: int, n_modes: int = 200) -> dict:
     return dict(vel=1, vel_modes=n_modes, vel_phi=u[:, 0].copy(), vel_theta=u[:, 1].copy())
 
 
-# Table 0 of the paper (N_sigma, N_rho, N_theta) and the power-of-two grids
-# that stand in for them here (n_tau x n_y = theta x rho)
+# Table 0 of the paper (N_sigma, N_rho, N_theta) and the grids used for them
+# here (n_tau x n_y = theta x rho): n_tau = N_theta itself (7 * 2^k), n_y the
+# power of two nearest N_rho (the y-transform takes powers of two; set 4's
+# 10000 rows would need 8192, above the 4096-row limit); the power-of-two
+# grids nearest both are kept as a second stand-in
 PAPER_SETS = {1: (300, 1250, 448), 2: (600, 2500, 896), 3: (1200, 5000, 1792), 4: (2400, 10000, 3584)}
-PAPER_SET_GRIDS = {1: (512, 1024), 2: (1024, 2048), 3: (2048, 4096)}
+PAPER_SET_GRIDS = {1: (448, 1024), 2: (896, 2048), 3: (1792, 4096)}
+PAPER_SET_POW2_GRIDS = {1: (512, 1024), 2: (1024, 2048), 3: (2048, 4096)}
 
 
 def paper_set(k: int, seed: int = 0, n_modes: int = 200, reg_eps: float = 2.0 ** -24,
-              n_steps: Optional[int] = None) -> Problem:
-    """The paper's workload (Sec. 4) on the power-of-two grid nearest to set k
-    of Table 0: sigma in [0, 120] with N_sigma steps, rho in [0, 400),
+              n_steps: Optional[int] = None, pow2: bool = False) -> Problem:
+    """The paper's workload (Sec. 4) on the grid of set k of Table 0
+    (PAPER_SET_GRIDS: N_theta tau-points, the power of two nearest N_rho
+    rows; pow2=True: PAPER_SET_POW2_GRIDS): sigma in [0, 120] with N_sigma
+    steps, rho in [0, 400),
     theta in [-13 pi, 15 pi), D/2 = 1/(4 pi), B = 0.05 (nl = -B), A = 3.4e-4,
     the random medium of Sec. 2 (seeded phases and angles), the regularised
     multiplier, and the paper's N-wave
     V0 = (theta - 3 pi)/(2 pi) (tanh(B/(4A)(theta - 4 pi)) - tanh(B/(4A)(theta - 2 pi)))."""
     n_sigma, _, _ = PAPER_SETS[k]
-    n_tau, n_y = PAPER_SET_GRIDS[k]
+    n_tau, n_y = (PAPER_SET_POW2_GRIDS if pow2 else PAPER_SET_GRIDS)[k]
     ns = n_sigma if n_steps is None else n_steps
     B, A = 0.05, 3.4e-4
     p = Problem(name="paper_set%d" % k, n_tau=n_tau, n_y=n_y, h=120.0 / n_sigma, n_steps=ns,

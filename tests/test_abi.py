@@ -54,6 +54,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(n_tau=48), 2), (dict(n_tau=16), 2), (dict(n_tau=16384), 2), (dict(n_y=8), 2), (dict(n_y=8192), 2),
+    (dict(n_tau=112), 2), (dict(n_tau=14336), 2), (dict(n_tau=96), 2), (dict(n_tau=480), 2), (dict(n_y=448), 2),
     (dict(h=0.0), 1), (dict(h=-1.0), 1), (dict(L_tau=0.0), 1), (dict(dtype=3), 1), (dict(A=-1.0), 1),
     (dict(weno_eps=0.0), 1), (dict(lf_scope=1), 1), (dict(cfl_max=-1.0), 1),
     (dict(scheme=2), 1), (dict(scheme=-1), 1), (dict(reg_eps=-1e-16), 1), (dict(reg_eps=float("nan")), 1),
@@ -66,6 +67,18 @@ def test_create_rejects_bad_parameters_before_device_work(kw, code):
     h = ctypes.c_void_p()
     assert L.kzk_create(ctypes.byref(p), 1, None, ctypes.byref(h)) == code
     assert not h.value
+
+
+def test_create_rejects_a_7_2k_plan_with_two_tau_lengths():
+    """n_tau = 7 * 2^k: every solve of the plan has that n_tau (checked
+    before any device work)."""
+    from paper_2103_06080_amd import kzk
+    L = kzk.lib()
+    for a, b in ((448, 512), (512, 448), (448, 896)):
+        ps = (kzk.Params * 2)(_params(n_tau=a), _params(n_tau=b))
+        h = ctypes.c_void_p()
+        assert L.kzk_create(ps, 2, None, ctypes.byref(h)) == 2, (a, b)
+        assert not h.value
 
 
 def test_null_arguments_rejected():
