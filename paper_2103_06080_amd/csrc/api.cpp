@@ -463,7 +463,12 @@ kzk_status check_range(const kzk_plan* p, long long first, long long n) {
 extern "C" {
 
 const char* kzk_status_str(kzk_status s) {
-    switch (s) {
+    // callers may pass any integer: read the bits as an int, not as the enum
+    // (a value outside the enumerators is not a valid kzk_status in C++)
+    static_assert(sizeof(kzk_status) == sizeof(int32_t), "kzk_status is passed as a 32-bit int");
+    int32_t v;
+    std::memcpy(&v, &s, sizeof(v));
+    switch (v) {
     case KZK_OK: return "ok";
     case KZK_ERR_ARG: return "invalid argument";
     case KZK_ERR_SIZE: return "grid size not supported";
