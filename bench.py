@@ -149,6 +149,11 @@ def _time(fn, sync):
     return time.perf_counter() - t0
 
 
+def progress(msg):
+    """One line on stderr as each leg of the benchmark ends."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def side_measurements(args, value_fp32, ms_fp32):
     """FP64 march of the same workload, the adjoint/forward time ratio on the
     2048 x 1024 adjoint workload, and the batched 64-solve throughput."""
@@ -171,6 +176,7 @@ def side_measurements(args, value_fp32, ms_fp32):
     v64 = p.points * p.n_steps / t
     out["fp64_c3"] = {"s_per_march": t, "value": v64, "fp32_speedup": value_fp32 / v64,
                       "y_threads": plan.y_threads}
+    progress("FP64 march done")
     plan.close()
     del plan, u, u0
     torch.cuda.empty_cache()
@@ -196,6 +202,7 @@ def side_measurements(args, value_fp32, ms_fp32):
                               "full_march_sampled_rows": rows,
                               "linear_march_vs_closed_form": {"fp32_state": linear_march_error(False),
                                                               "fp64_state": linear_march_error(True)}}
+    progress("FP32 march with FP64 state done")
     # adjoint / forward on the adjoint workload (FP32 and FP64); its 8 / 16 MB
     # arrays fit the 256 MB Infinity Cache, so these rates are cache-assisted
     q = inputs.c5()
@@ -212,6 +219,7 @@ def side_measurements(args, value_fp32, ms_fp32):
         assert plan.poll() == 0
         out["adjoint_c5_" + dt] = {"fwd_s": tf, "adjoint_s": ta, "adjoint_over_fwd": ta / tf,
                                    "ckpt_every": inputs.C5_CKPT, "cache_assisted": True}
+        progress("adjoint %s done" % dt)
         plan.close()
         del plan
     torch.cuda.empty_cache()
@@ -231,6 +239,7 @@ def side_measurements(args, value_fp32, ms_fp32):
     pts = sum(pp.points for pp in probs)
     out["batched_c4_f32"] = {"solves": len(probs), "points": pts, "s_per_march": tb,
                              "value": pts * 500 / tb, "graph": True, "autotuned": plan.tuning()}
+    progress("batched march done")
     plan.close()
     del plan, u, u0
     torch.cuda.empty_cache()
@@ -273,14 +282,16 @@ PAPER_CUDA_FP32_S = {1: 0.5564, 2: 3.788, 3: 28.31}
 
 def paper_sets():
     """The paper's workload (full b with transport by the random medium,
-    regularised multiplier) on the power-of-two stand-in grids of sets 1-3,
-    each run for its N_sigma steps in FP32 with per-kernel events on every 8th
-    step; the paper's own times are on its larger 7 * 2^k grids."""
+    regularised multiplier) on the grids of sets 1-3 (n_tau = N_theta = 7 2^k,
+    n_y the power of two nearest N_rho) and on the power-of-two grids nearest
+    them ("_pow2"), each run for its N_sigma steps in FP32 with per-kernel
+    events on every 8th step.  value: grid-point-steps/s; paper_value: the
+    same for the paper's CUDA FP32 time on its own grid (N_rho rows)."""
     import torch
     from paper_2103_06080_amd import inputs, kzk
     res = {}
-    for k in (1, 2, 3):
-        p = inputs.paper_set(k)
+    for k, pow2 in ((1, False), (2, False), (3, False), (1, True), (2, True), (3, True)):
+        p = inputs.paper_set(k, pow2=pow2)
         plan = kzk.Plan(p, dtype="f32")
         u0 = plan.pack([p.u0])
         u = u0.clone()
@@ -299,7 +310,7 @@ def paper_sets():
         plan.profile(False)
         assert plan.poll() == 0
         ns, nrho, nth = inputs.PAPER_SETS[k]
-        res["set%d" % k] = {"grid": [p.n_tau, p.n_y], "steps": p.n_steps, "s": t,
+        res["set%d%s" % (k, "_pow2" if pow2 else "")] = {"grid": [p.n_tau, p.n_y], "steps": p.n_steps, "s": t,
                             "value": p.points * p.n_steps / t,
                             "kernels_avg_us": {kk: round(1e3 * v[0] / v[1], 1) for kk, v in prof.items()},
                             "paper_grid": [nth, nrho], "paper_cuda_fp32_s": PAPER_CUDA_FP32_S[k],
@@ -307,6 +318,7 @@ def paper_sets():
         plan.close()
         del plan, u, u0
         torch.cuda.empty_cache()
+        progress("paper set %d%s done" % (k, " (power-of-two grid)" if pow2 else ""))
     return res
 
 
@@ -321,6 +333,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--y-threads", type=int, default=0, help="y-pass block size (0: plan default)")
     ap.add_argument("--tau-threads", type=int, default=0, help="tau-pass block size (0: plan default)")
+    ap.add_argument("--tau-fft-radix", type=int, default=0, choices=[0, 8, 16],
+                    help="radix schedule of the tau-transforms (0: plan default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for memory counters)")
     ap.add_argument("--march-steps", type=int, default=0, help="override the steps of one march (profiling)")
@@ -350,7 +364,8 @@ def main():
     prob = make()
     steps_per_march = min(args.march_steps or prob.n_steps, prob.n_steps)
 
-    plan = kzk.Plan(prob, dtype=args.dtype, y_threads=args.y_threads or None, tau_threads=args.tau_threads or None)
+    plan = kzk.Plan(prob, dtype=args.dtype, y_threads=args.y_threads or None, tau_threads=args.tau_threads or None,
+                    tau_fft_radix=args.tau_fft_radix or None)
     u0 = plan.pack([prob.u0])
     u = torch.empty_like(u0)
     torch.cuda.synchronize()
@@ -385,6 +400,7 @@ def main():
     assert np.isfinite(u_host).all()
 
     elapsed = t1 - t0
+    progress("timed marches done (%.1f ms each)" % (1e3 * elapsed / args.steps))
     ms_per_step = 1e3 * elapsed / args.steps
     pts_steps = prob.points * steps_per_march * args.steps
     value = pts_steps / elapsed

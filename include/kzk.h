@@ -166,17 +166,27 @@ kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
  * 256 only with n_tau = 7 * 2^k.  0 restores the default (256). */
 kzk_status kzk_set_tau_threads(kzk_plan *plan, int32_t threads);
 
+/* Select the radix schedule of the power-of-two tau-transforms: 16
+ * (radix-16 stages, then one radix-2/4/8 tail; the default) or 8 (radix-8
+ * stages, then one radix-2/4 tail: one more LDS pass per transform, half the
+ * values per butterfly in registers).  16 only with n_tau = 7 * 2^k.
+ * 0 restores the default.  KZK_ERR_ARG for other values. */
+kzk_status kzk_set_tau_fft_radix(kzk_plan *plan, int32_t radix);
+int32_t kzk_get_tau_fft_radix(const kzk_plan *plan);
+
 /* Autotuner: time n_trial steps on the plan's own scratch state (u_dev is
- * read, never written) for every supported pair of y-pass and tau-pass block
- * sizes, keep the fastest pair and return its y-pass block size (> 0), or
- * -(kzk_status) on error.  The y-pass block size fixes the column-tile width
+ * read, never written) for every supported combination of y-pass block
+ * size, tau-pass block size and tau-transform radix schedule, keep the
+ * fastest and return its y-pass block size (> 0), or -(kzk_status) on
+ * error.  The y-pass block size fixes the column-tile width
  * W = threads * 16 / n_y of the y-FFTs and of the spectral layout (and so
  * the row segments of the tau-pass); the tau-pass block size fixes how many
  * tau-lines one block transforms and differentiates together.  If the
  * environment variable KZK_TUNE_CACHE names a file, a plan whose key (device
  * architecture, dtype, scheme, every solve's grid) is listed there takes the
- * stored pair without timing, and a timed result is appended to it as the
- * text line "<key> <y_threads> <tau_threads> <ms per step>".  Synchronises. */
+ * stored choice without timing, and a timed result is appended to it as the
+ * text line "<key> <y_threads> <tau_threads> <tau_fft_radix> <ms per step>".
+ * Synchronises. */
 int32_t kzk_autotune(kzk_plan *plan, const void *u_dev, int32_t n_trial);
 
 /* Current y-pass block size. */

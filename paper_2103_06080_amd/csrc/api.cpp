@@ -74,6 +74,7 @@ struct kzk_plan {
     YItem* dY = nullptr;
     int n_tau_items = 0, n_tau_adj_items = 0, n_y_items = 0, max_tau_items = 0;
     int tau_threads = kzk::TAU_THREADS;   // tau-pass block size
+    int tau_mr = 4;                       // tau-transform radix schedule: log2 of the largest radix (4 or 3)
     void* dTwSt = nullptr;      // per-stage Stockham twiddles
     unsigned* dStatus = nullptr;
     double* dSched = nullptr;
@@ -338,10 +339,10 @@ hipError_t tau(kzk_plan* p, int mode, const void* u_in, void* u_out, const void*
     if (p->dtype == KZK_F32)
         return kzk::launch_tau<float>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const float*)u_in,
                                       (float*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
-                                      p->tau_prog, p->gk, p->dStatus, p->stream);
+                                      p->tau_prog, p->gk, p->tau_mr, p->dStatus, p->stream);
     return kzk::launch_tau<double>(mode, p->tau_threads, p->dDesc, p->dTau, p->n_tau_items, (const double*)u_in,
                                    (double*)u_out, Cin, Bout, p->dTw, p->dTwSt, p->log2_ntw, node, tiled,
-                                   p->tau_prog, p->gk, p->dStatus, p->stream);
+                                   p->tau_prog, p->gk, p->tau_mr, p->dStatus, p->stream);
 }
 
 // step: the ExpRK22 step, for instances with a D schedule (the y-pass
@@ -741,6 +742,19 @@ kzk_status kzk_set_tau_threads(kzk_plan* p, int32_t threads) {
 }
 
 
+int32_t kzk_get_tau_fft_radix(const kzk_plan* p) { return p ? 1 << p->tau_mr : 0; }
+
+kzk_status kzk_set_tau_fft_radix(kzk_plan* p, int32_t radix) {
+    if (!p) return KZK_ERR_ARG;
+    if (radix == 0) radix = 16;
+    if (radix != 16 && radix != 8) return KZK_ERR_ARG;
+    if (p->gk && radix != 16) return KZK_ERR_ARG;   // lengths 7 * 2^K: one schedule
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
+    drop_graph(p);
+    p->tau_mr = radix == 16 ? 4 : 3;
+    return KZK_OK;
+}
+
 kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
     if (!p) return KZK_ERR_ARG;
     if (threads == 0) threads = default_y_threads(p);
@@ -923,15 +937,16 @@ std::string tune_key(const kzk_plan* p) {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
-    std::string k = "kzk1|" + arch + (p->dtype == KZK_F32 ? "|f32|" : "|f64|") + std::to_string(p->scheme);
+    std::string k = "kzk2|" + arch + (p->dtype == KZK_F32 ? "|f32|" : "|f64|") + std::to_string(p->scheme);
     for (const InstDesc& d : p->desc)
         k += "|" + std::to_string(d.n_tau) + "x" + std::to_string(d.n_y) + (d.D_step ? "s" : "") +
              (d.reg_eps > 0 ? "r" : "");
     return k;
 }
 
-// Look the key up in the cache file: the last line "<key> <y_threads> <tau_threads> <ms>" wins.
-bool tune_lookup(const char* path, const std::string& key, int* yt, int* tt) {
+// Look the key up in the cache file: the last line
+// "<key> <y_threads> <tau_threads> <tau_fft_radix> <ms>" wins.
+bool tune_lookup(const char* path, const std::string& key, int* yt, int* tt, int* rx) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     bool found = false;
@@ -940,10 +955,11 @@ bool tune_lookup(const char* path, const std::string& key, int* yt, int* tt) {
         const char* sp = std::strchr(line.data(), ' ');
         if (!sp || (size_t)(sp - line.data()) != key.size() || std::strncmp(line.data(), key.c_str(), key.size()))
             continue;
-        int a = 0, b = 0;
-        if (std::sscanf(sp + 1, "%d %d", &a, &b) == 2) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(sp + 1, "%d %d %d", &a, &b, &c) == 3) {
             *yt = a;
             *tt = b;
+            *rx = c;
             found = true;
         }
     }
@@ -951,10 +967,10 @@ bool tune_lookup(const char* path, const std::string& key, int* yt, int* tt) {
     return found;
 }
 
-void tune_store(const char* path, const std::string& key, int yt, int tt, float ms) {
+void tune_store(const char* path, const std::string& key, int yt, int tt, int rx, float ms) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %.4f\n", key.c_str(), yt, tt, (double)ms);
+    std::fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), yt, tt, rx, (double)ms);
     std::fclose(f);
 }
 
@@ -971,17 +987,21 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
     auto tau_ok = [&](int t) {
         return kzk::tau_threads_supported(p->dtype == KZK_F64, t) && (!p->gk || t == kzk::TAU_THREADS);
     };
+    auto radix_ok = [&](int r) { return r == 16 || (r == 8 && !p->gk); };
     if (cache && *cache) {
-        int yt = 0, tt = 0;
-        if (tune_lookup(cache, key, &yt, &tt) && kzk::y_threads_supported(p->dtype == KZK_F64, yt) && tau_ok(tt)) {
-            if ((st = kzk_set_y_threads(p, yt)) != KZK_OK || (st = kzk_set_tau_threads(p, tt)) != KZK_OK)
+        int yt = 0, tt = 0, rx = 0;
+        if (tune_lookup(cache, key, &yt, &tt, &rx) && kzk::y_threads_supported(p->dtype == KZK_F64, yt) &&
+            tau_ok(tt) && radix_ok(rx)) {
+            if ((st = kzk_set_y_threads(p, yt)) != KZK_OK || (st = kzk_set_tau_threads(p, tt)) != KZK_OK ||
+                (st = kzk_set_tau_fft_radix(p, rx)) != KZK_OK)
                 return -(int32_t)st;
             return yt;
         }
     }
     const int ycands[3] = {1024, 512, 256};
     const int tcands[2] = {kzk::TAU_THREADS_WIDE, kzk::TAU_THREADS};
-    int best_y = p->y_threads, best_t = p->tau_threads;
+    const int rcands[2] = {16, 8};
+    int best_y = p->y_threads, best_t = p->tau_threads, best_r = 1 << p->tau_mr;
     float best_ms = 1e30f;
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -(int32_t)KZK_ERR_DEVICE;
@@ -993,17 +1013,22 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
         for (int t : tcands) {
             if (!tau_ok(t)) continue;
             if ((st = kzk_set_tau_threads(p, t)) != KZK_OK) break;
-            // one untimed step to warm up, then n_trial timed steps, on the plan's own state
-            if ((st = enqueue_forward(p, u)) != KZK_OK) break;
-            if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
-            if ((st = enqueue_forward(p, u)) != KZK_OK) break;
-            (void)hipEventRecord(a, p->stream);
-            if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
-            (void)hipEventRecord(b, p->stream);
-            if (hipEventSynchronize(b) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, a, b);
-            if (ms < best_ms) { best_ms = ms; best_y = c; best_t = t; }
+            for (int r : rcands) {
+                if (!radix_ok(r)) continue;
+                if ((st = kzk_set_tau_fft_radix(p, r)) != KZK_OK) break;
+                // one untimed step to warm up, then n_trial timed steps, on the plan's own state
+                if ((st = enqueue_forward(p, u)) != KZK_OK) break;
+                if ((st = enqueue_steps(p, 0, 1)) != KZK_OK) break;
+                if ((st = enqueue_forward(p, u)) != KZK_OK) break;
+                (void)hipEventRecord(a, p->stream);
+                if ((st = enqueue_steps(p, 0, n_trial)) != KZK_OK) break;
+                (void)hipEventRecord(b, p->stream);
+                if (hipEventSynchronize(b) != hipSuccess) { st = KZK_ERR_DEVICE; break; }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (ms < best_ms) { best_ms = ms; best_y = c; best_t = t; best_r = r; }
+            }
+            if (st != KZK_OK) break;
         }
         if (st != KZK_OK) break;
     }
@@ -1012,9 +1037,10 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
     (void)hipEventDestroy(b);
     (void)hipMemset(p->dStatus, 0, sizeof(unsigned));   // trial steps ran on scratch state
     if (st != KZK_OK) return -(int32_t)st;
-    if ((st = kzk_set_y_threads(p, best_y)) != KZK_OK || (st = kzk_set_tau_threads(p, best_t)) != KZK_OK)
+    if ((st = kzk_set_y_threads(p, best_y)) != KZK_OK || (st = kzk_set_tau_threads(p, best_t)) != KZK_OK ||
+        (st = kzk_set_tau_fft_radix(p, best_r)) != KZK_OK)
         return -(int32_t)st;
-    if (cache && *cache) tune_store(cache, key, best_y, best_t, best_ms / (float)n_trial);
+    if (cache && *cache) tune_store(cache, key, best_y, best_t, best_r, best_ms / (float)n_trial);
     return best_y;
 }
 

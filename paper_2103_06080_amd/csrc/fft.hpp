@@ -141,56 +141,67 @@ __host__ __device__ constexpr int padded(int n) { return n + n / 16; }
 // ---------------------------------------------------------------- Stockham stages
 // A length-n transform (n = 2^LN, 16 <= n <= 8192) at logical LDS positions
 // base + idx (base a multiple of 16), done by n/16 threads t, each holding 16
-// elements per stage: radix-16 stages first, then one tail stage of radix
-// 2, 4 or 8.  Stage sizes are compile-time, so every LDS access of a thread
-// is one padded base address plus an immediate offset.  A stage reads the
-// inputs of all its butterflies, waits, then writes the outputs (in place).
-// Twiddles of the stage with span Ns*R come from a per-stage table
+// elements per stage.  Radix schedule MR (log2 of the largest radix): stages
+// of radix 2^MR first (MR = 4: radix 16; MR = 3: radix 8, two butterflies per
+// thread), then one tail stage of a smaller power of two.  Stage sizes are
+// compile-time, so every LDS access of a thread is one padded base address
+// plus an immediate offset.  A stage reads the inputs of all its
+// butterflies, waits, then writes the outputs (in place).  Twiddles of the
+// stage with span Ns*R come from a per-stage table
 // twst[off + s*Ns + k] = exp(-2 pi i k s / (Ns R)) (k < Ns, s < R), s-major so
-// that the lanes of a wave (consecutive k) read consecutive entries.
+// that the lanes of a wave (consecutive k) read consecutive entries; the
+// table holds the stages of every length of the MR = 4 schedule, then those
+// of the MR = 3 schedule.
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
+constexpr int CT_MIN_LN = 4, CT_MAX_LN = 13;
+
+// radix (log2) of the stage starting at Ns = 2^LG of a length-2^LN transform
+__host__ __device__ constexpr int ct_radix(int LN, int LG, int MR = 4) { return (LN - LG) >= MR ? MR : (LN - LG); }
+
 // sum of Ns*R over the stages with Ns > 1 of a length-2^LN transform
-__host__ __device__ constexpr int ct_stage_span_sum(int LN) {
+__host__ __device__ constexpr int ct_stage_span_sum(int LN, int MR = 4) {
     int tot = 0, lg = 0;
     while (lg < LN) {
-        const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
+        const int lr = ct_radix(LN, lg, MR);
         if (lg > 0) tot += 1 << (lg + lr);
         lg += lr;
     }
     return tot;
 }
-// offset of the stage starting at Ns = 2^LG in the table of all sizes 2^4..2^13
-__host__ __device__ constexpr int ct_stage_offset(int LN, int LG) {
+// entries of the stages of all lengths 2^4 .. 2^13 of one schedule
+__host__ __device__ constexpr int ct_schedule_size(int MR) {
     int o = 0;
-    for (int l = 4; l < LN; ++l) o += ct_stage_span_sum(l);
+    for (int l = CT_MIN_LN; l <= CT_MAX_LN; ++l) o += ct_stage_span_sum(l, MR);
+    return o;
+}
+// offset of the stage starting at Ns = 2^LG (schedule MR) in the table
+__host__ __device__ constexpr int ct_stage_offset(int LN, int LG, int MR = 4) {
+    int o = MR == 4 ? 0 : ct_schedule_size(4);
+    for (int l = CT_MIN_LN; l < LN; ++l) o += ct_stage_span_sum(l, MR);
     int lg = 0;
     while (lg < LG) {
-        const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
+        const int lr = ct_radix(LN, lg, MR);
         if (lg > 0) o += 1 << (lg + lr);
         lg += lr;
     }
     return o;
 }
-constexpr int CT_MIN_LN = 4, CT_MAX_LN = 13;
-constexpr int CT_TABLE_SIZE = ct_stage_offset(CT_MAX_LN + 1, 0);
-
-// radix (log2) of the stage starting at Ns = 2^LG of a length-2^LN transform
-__host__ __device__ constexpr int ct_radix(int LN, int LG) { return (LN - LG) >= 4 ? 4 : (LN - LG); }
+constexpr int CT_TABLE_SIZE = ct_schedule_size(4) + ct_schedule_size(3);
 
 // The twiddles a thread needs in the stage starting at Ns = 2^LG: PER blocks
 // of R - 1 values (at most 15), w[b * (R - 1) + s - 1] for s = 1 .. R-1.
-template <typename T, int S, int LN, int LG>
+template <typename T, int S, int LN, int LG, int MR = 4>
 __device__ __forceinline__ void ct_fetch(const cpx<T>* __restrict__ twst, int t, bool active, cpx<T> (&w)[15]) {
     if constexpr (LG > 0 && LG < LN) {
-        constexpr int LR = ct_radix(LN, LG), R = 1 << LR, PER = 16 / R, tpr = (1 << LN) >> 4, Ns = 1 << LG;
+        constexpr int LR = ct_radix(LN, LG, MR), R = 1 << LR, PER = 16 / R, tpr = (1 << LN) >> 4, Ns = 1 << LG;
         // every thread loads (the index is in range for any t): a load under a
         // branch would make the compiler wait for it at the branch's join
         (void)active;
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
-            const cpx<T>* p = twst + ct_stage_offset(LN, LG) + ((t + b * tpr) & (Ns - 1));
+            const cpx<T>* p = twst + ct_stage_offset(LN, LG, MR) + ((t + b * tpr) & (Ns - 1));
             #pragma unroll
             for (int s = 1; s < R; ++s) w[b * (R - 1) + s - 1] = twiddle<S>(p, s * Ns);
         }
@@ -205,14 +216,14 @@ __device__ __forceinline__ void ct_fetch(const cpx<T>* __restrict__ twst, int t,
 // caller; an inverse transform multiplies by their conjugates.
 enum { TW_OWN = 0, TW_AHEAD = 1, TW_HELD = 2 };
 
-template <typename T, int S, int TW, int LN, int LG, int LR>
+template <typename T, int S, int TW, int LN, int LG, int LR, int MR = 4>
 __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
                                          cpx<T> (&wc)[15], cpx<T> (&wn)[15]) {
     constexpr int n = 1 << LN, tpr = n >> 4, R = 1 << LR, PER = 16 / R, nR = n / R, Ns = 1 << LG;
     if constexpr (TW == TW_AHEAD)
-        ct_fetch<T, S, LN, LG + LR>(twst, t, active, wn);
+        ct_fetch<T, S, LN, LG + LR, MR>(twst, t, active, wn);
     else if constexpr (TW == TW_OWN)
-        ct_fetch<T, S, LN, LG>(twst, t, active, wc);
+        ct_fetch<T, S, LN, LG, MR>(twst, t, active, wc);
     cpx<T> v[PER][R];
     if (active) {
         #pragma unroll
@@ -242,7 +253,8 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
             }
             Dft<T, R, S>::run(v[b]);
             if constexpr (Ns == 1) {
-                static_assert(R == 16, "first stage is radix 16");
+                // j R .. j R + R - 1 lie in one run of 16 slots (R divides 16)
+                static_assert(R >= 8 && R <= 16, "first stage is radix 16 or 8");
                 const int p = padi(base + j * R);
                 #pragma unroll
                 for (int s = 0; s < R; ++s) buf[p + s] = v[b][s];
@@ -259,21 +271,21 @@ __device__ __forceinline__ void ct_stage(cpx<T>* buf, int base, int t, bool acti
     __syncthreads();
 }
 
-template <typename T, int S, int TW, int LN, int LG>
+template <typename T, int S, int TW, int LN, int LG, int MR>
 __device__ __forceinline__ void ct_stages(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst,
                                           cpx<T> (&wc)[15]) {
     if constexpr (LG < LN) {
-        constexpr int LR = ct_radix(LN, LG);
+        constexpr int LR = ct_radix(LN, LG, MR);
         cpx<T> wn[15];
-        ct_stage<T, S, TW, LN, LG, LR>(buf, base, t, active, twst, wc, wn);
-        ct_stages<T, S, TW, LN, LG + LR>(buf, base, t, active, twst, wn);
+        ct_stage<T, S, TW, LN, LG, LR, MR>(buf, base, t, active, twst, wc, wn);
+        ct_stages<T, S, TW, LN, LG + LR, MR>(buf, base, t, active, twst, wn);
     }
 }
 
-template <typename T, int S, int TW, int LN>
+template <typename T, int S, int TW, int LN, int MR = 4>
 __device__ __forceinline__ void ct_fft(cpx<T>* buf, int base, int t, bool active, const cpx<T>* __restrict__ twst) {
     cpx<T> w0[15];   // the first stage (Ns = 1) has no twiddles
-    ct_stages<T, S, TW, LN, 0>(buf, base, t, active, twst, w0);
+    ct_stages<T, S, TW, LN, 0, MR>(buf, base, t, active, twst, w0);
 }
 
 // Held twiddles: the stages with Ns > 1 of a length-2^LN transform
@@ -344,20 +356,22 @@ __device__ __forceinline__ void lds_fft_held(cpx<T>* buf, int base, int n, int t
 // logical LDS positions base .. base+n-1 (base a multiple of 16), done by the
 // threads t < n/16 where `active`; every thread of the block must call it.
 // S = -1: forward, S = +1: inverse (unnormalised).  LA: twiddle look-ahead.
-template <typename T, int S, bool LA = true>
+// MR: the radix schedule (4: radix-16 stages, 3: radix-8 stages).
+template <typename T, int S, bool LA = true, int MR = 4>
 __device__ __forceinline__ void lds_fft(cpx<T>* buf, int base, int n, int t, bool active,
                                         const cpx<T>* __restrict__ twst) {
+    constexpr int TW = LA ? TW_AHEAD : TW_OWN;
     switch (ilog2(n)) {
-    case 4: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 4>(buf, base, t, active, twst); break;
-    case 5: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 5>(buf, base, t, active, twst); break;
-    case 6: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 6>(buf, base, t, active, twst); break;
-    case 7: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 7>(buf, base, t, active, twst); break;
-    case 8: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 8>(buf, base, t, active, twst); break;
-    case 9: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 9>(buf, base, t, active, twst); break;
-    case 10: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 10>(buf, base, t, active, twst); break;
-    case 11: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 11>(buf, base, t, active, twst); break;
-    case 12: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 12>(buf, base, t, active, twst); break;
-    default: ct_fft<T, S, LA ? TW_AHEAD : TW_OWN, 13>(buf, base, t, active, twst); break;
+    case 4: ct_fft<T, S, TW, 4, MR>(buf, base, t, active, twst); break;
+    case 5: ct_fft<T, S, TW, 5, MR>(buf, base, t, active, twst); break;
+    case 6: ct_fft<T, S, TW, 6, MR>(buf, base, t, active, twst); break;
+    case 7: ct_fft<T, S, TW, 7, MR>(buf, base, t, active, twst); break;
+    case 8: ct_fft<T, S, TW, 8, MR>(buf, base, t, active, twst); break;
+    case 9: ct_fft<T, S, TW, 9, MR>(buf, base, t, active, twst); break;
+    case 10: ct_fft<T, S, TW, 10, MR>(buf, base, t, active, twst); break;
+    case 11: ct_fft<T, S, TW, 11, MR>(buf, base, t, active, twst); break;
+    case 12: ct_fft<T, S, TW, 12, MR>(buf, base, t, active, twst); break;
+    default: ct_fft<T, S, TW, 13, MR>(buf, base, t, active, twst); break;
     }
 }
 
@@ -380,7 +394,14 @@ __device__ __forceinline__ void gen_stage(cpx<T>* buf, int base, int t, bool act
     if constexpr (NS > 1) {
         #pragma unroll
         for (int b = 0; b < PER; ++b) {
-            const int k = (t + b * tpr) % NS;
+            // the index passes through an empty asm statement, so the loads
+            // stay in this stage: with every address known at compile time
+            // the compiler would otherwise issue the twiddle loads of all
+            // stages at the start of the kernel and hold them in registers
+            // through the WENO part (170 instead of 111 VGPRs, half the
+            // waves per SIMD)
+            int k = (t + b * tpr) % NS;
+            asm volatile("" : "+v"(k));
             #pragma unroll
             for (int s = 1; s < R; ++s) w[b][s - 1] = twiddle<S>(tw, s * k * TS);
         }

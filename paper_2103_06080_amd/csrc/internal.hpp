@@ -61,11 +61,13 @@ constexpr int YW_THREADS = 256;
 // progression indexing in the mode-2 kernel).
 // nt: threads per block (tau_threads_supported).  gk > 0: every instance
 // has M = 7 * 2^gk (4 <= gk <= 9), nt = TAU_THREADS, tw holds
-// exp(-2 pi i k / n_tau) for k < n_tau, and twst, log2_ntw and prog are unused.
+// exp(-2 pi i k / n_tau) for k < n_tau, and twst, log2_ntw, prog and mr are
+// unused.  mr: radix schedule of the power-of-two tau-transforms (log2 of the
+// largest radix, 4 or 3).
 template <typename T>
 hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, int prog, int gk, unsigned* status, hipStream_t s);
+                      int node, int tiled, int prog, int gk, int mr, unsigned* status, hipStream_t s);
 bool tau_threads_supported(int dtype_is_f64, int nt);
 
 // y-pass over n_items column tiles with at most max_blocks persistent blocks

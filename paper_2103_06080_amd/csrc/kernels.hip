@@ -474,7 +474,8 @@ __device__ __forceinline__ void r2c_post_gen(const cpx<T>* lds, int base, cpx<T>
 // M = 7 * 2^GK (n_tau = 7 * 2^(GK+1)); its M/16 threads per line sit in an
 // aligned group of 2^(GK-1) (the rest of the group idle), so the block holds
 // NTT / 2^(GK-1) lines, and tw is the table e^{-2 pi i k / n_tau}, k < n_tau.
-template <typename T, int MODE, bool PROG = false, int NTT = TAU_THREADS, int GK = 0>
+// MR: radix schedule of the power-of-two transforms (4: radix 16, 3: radix 8).
+template <typename T, int MODE, bool PROG = false, int NTT = TAU_THREADS, int GK = 0, int MR = 4>
 __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ descs,
                                                   const TauItem* __restrict__ items,
                                                   const T* __restrict__ u_in, T* __restrict__ u_out,
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
             gen_fft<T, -1, GK>(lds, base, t, active, tw);
             if (active) r2c_post_gen<T, (7 << GK)>(lds, base, Bout + so, ix, t, tw);
         } else {
-            lds_fft<T, -1>(lds, base, M, t, active, twst);
+            lds_fft<T, -1, true, MR>(lds, base, M, t, active, twst);
             if (active) r2c_post(lds, base, Bout + so, ix, M, t, tpr, tw, log2_ntw);
         }
         return;
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
     }
     __syncthreads();
     if constexpr (GK > 0) gen_fft<T, 1, GK>(lds, base, t, active, tw);
-    else lds_fft<T, 1>(lds, base, M, t, active, twst);
+    else lds_fft<T, 1, true, MR>(lds, base, M, t, active, twst);
 
     if (MODE == 1 || MODE == 3) {
         quad<T>* ug = reinterpret_cast<quad<T>*>(u_out + d.off_u + (long long)row * N);
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(NTT) void tau_kernel(const InstDesc* __restrict__ d
         gen_fft<T, -1, GK>(lds, base, t, active, tw);
         if (active) r2c_post_gen<T, (7 << GK)>(lds, base, Bout + so, ix, t, tw);
     } else {
-        lds_fft<T, -1>(lds, base, M, t, active, twst);
+        lds_fft<T, -1, true, MR>(lds, base, M, t, active, twst);
         if (active) {
             if constexpr (PROG) r2c_post_prog(lds, base, Bout + d.off_state, (unsigned)row << d.log2W, ix, M, t, tpr,
                                               tw, log2_ntw);
@@ -1772,7 +1773,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const InstDesc* __restrict_
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T, int NTT>
+template <typename T, int NTT, int MR>
 static hipError_t launch_tau_nt(int mode, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                                 T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
                                 int node, int tiled, int prog, unsigned* status, hipStream_t s) {
@@ -1782,17 +1783,17 @@ static hipError_t launch_tau_nt(int mode, const InstDesc* d_desc, const TauItem*
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((tau_kernel<T, 0, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
-    case 1: hipLaunchKernelGGL((tau_kernel<T, 1, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 0: hipLaunchKernelGGL((tau_kernel<T, 0, false, NTT, 0, MR>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 1: hipLaunchKernelGGL((tau_kernel<T, 1, false, NTT, 0, MR>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     case 2:
         if (prog && tiled)
-            hipLaunchKernelGGL((tau_kernel<T, 2, true, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
+            hipLaunchKernelGGL((tau_kernel<T, 2, true, NTT, 0, MR>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
                                ws, log2_ntw, node, tiled, status);
         else
-            hipLaunchKernelGGL((tau_kernel<T, 2, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
+            hipLaunchKernelGGL((tau_kernel<T, 2, false, NTT, 0, MR>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w,
                                ws, log2_ntw, node, tiled, status);
         break;
-    case 3: hipLaunchKernelGGL((tau_kernel<T, 3, false, NTT>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
+    case 3: hipLaunchKernelGGL((tau_kernel<T, 3, false, NTT, 0, MR>), g, b, 0, s, d_desc, d_items, u_in, u_out, ci, bo, w, ws, log2_ntw, node, tiled, status); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1821,8 +1822,9 @@ bool tau_threads_supported(int is_f64, int nt) { return nt == TAU_THREADS || (nt
 template <typename T>
 hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d_items, int n_items, const T* u_in,
                       T* u_out, const void* Cin, void* Bout, const void* tw, const void* twst, int log2_ntw,
-                      int node, int tiled, int prog, int gk, unsigned* status, hipStream_t s) {
+                      int node, int tiled, int prog, int gk, int mr, unsigned* status, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (mr != 3 && mr != 4) return hipErrorInvalidValue;
     if (gk != 0) {
         if (nt != TAU_THREADS) return hipErrorInvalidValue;
         switch (gk) {
@@ -1836,12 +1838,18 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
         }
     }
     if (nt == TAU_THREADS)
-        return launch_tau_nt<T, TAU_THREADS>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw, twst,
-                                             log2_ntw, node, tiled, prog, status, s);
+        return mr == 4 ? launch_tau_nt<T, TAU_THREADS, 4>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw,
+                                                          twst, log2_ntw, node, tiled, prog, status, s)
+                       : launch_tau_nt<T, TAU_THREADS, 3>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw,
+                                                          twst, log2_ntw, node, tiled, prog, status, s);
     if constexpr (sizeof(T) == 4) {
         if (nt == TAU_THREADS_WIDE)
-            return launch_tau_nt<T, TAU_THREADS_WIDE>(mode, d_desc, d_items, n_items, u_in, u_out, Cin, Bout, tw,
-                                                      twst, log2_ntw, node, tiled, prog, status, s);
+            return mr == 4 ? launch_tau_nt<T, TAU_THREADS_WIDE, 4>(mode, d_desc, d_items, n_items, u_in, u_out, Cin,
+                                                                   Bout, tw, twst, log2_ntw, node, tiled, prog,
+                                                                   status, s)
+                           : launch_tau_nt<T, TAU_THREADS_WIDE, 3>(mode, d_desc, d_items, n_items, u_in, u_out, Cin,
+                                                                   Bout, tw, twst, log2_ntw, node, tiled, prog,
+                                                                   status, s);
     }
     return hipErrorInvalidValue;
 }
@@ -2078,27 +2086,28 @@ hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* 
 int stage_twiddle_entries() { return CT_TABLE_SIZE; }
 
 void stage_twiddles(double* out) {
-    for (int LN = CT_MIN_LN; LN <= CT_MAX_LN; ++LN) {
-        int lg = 0;
-        while (lg < LN) {
-            const int lr = (LN - lg) >= 4 ? 4 : (LN - lg);
-            if (lg > 0) {
-                const int off = ct_stage_offset(LN, lg), Ns = 1 << lg, R = 1 << lr;
-                for (int kk = 0; kk < Ns; ++kk)
-                    for (int s = 0; s < R; ++s) {
-                        const double a = -2.0 * KZK_PI * (double)(kk * s) / (double)(Ns * R);
-                        out[2 * (off + s * Ns + kk)] = cos(a);
-                        out[2 * (off + s * Ns + kk) + 1] = sin(a);
-                    }
+    for (int MR = 4; MR >= 3; --MR)
+        for (int LN = CT_MIN_LN; LN <= CT_MAX_LN; ++LN) {
+            int lg = 0;
+            while (lg < LN) {
+                const int lr = ct_radix(LN, lg, MR);
+                if (lg > 0) {
+                    const int off = ct_stage_offset(LN, lg, MR), Ns = 1 << lg, R = 1 << lr;
+                    for (int kk = 0; kk < Ns; ++kk)
+                        for (int s = 0; s < R; ++s) {
+                            const double a = -2.0 * KZK_PI * (double)(kk * s) / (double)(Ns * R);
+                            out[2 * (off + s * Ns + kk)] = cos(a);
+                            out[2 * (off + s * Ns + kk) + 1] = sin(a);
+                        }
+                }
+                lg += lr;
             }
-            lg += lr;
         }
-    }
 }
 
 #define KZK_INSTANTIATE(T)                                                                                          \
     template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
-                                      void*, const void*, const void*, int, int, int, int, int, unsigned*,          \
+                                      void*, const void*, const void*, int, int, int, int, int, int, unsigned*,     \
                                       hipStream_t);                                                                 \
     template hipError_t launch_y<T>(int, int, int, int, const InstDesc*, const YItem*, int, int, void*,             \
                                     const void*, const void*, void*, void*, void*, const void*, int, hipStream_t);   \

@@ -23,7 +23,7 @@ EXPORTS = ["kzk_create", "kzk_step", "kzk_adjoint", "kzk_poll", "kzk_inst_offset
            "kzk_set_graph", "kzk_set_y_threads", "kzk_get_y_threads", "kzk_destroy", "kzk_status_str",
            "kzk_eval_b", "kzk_tau_forward", "kzk_tau_inverse", "kzk_profile_enable", "kzk_profile_read",
            "kzk_read_tables", "kzk_autotune", "kzk_step_noalloc", "kzk_set_tau_threads",
-           "kzk_get_tau_threads"]
+           "kzk_get_tau_threads", "kzk_set_tau_fft_radix", "kzk_get_tau_fft_radix"]
 KINDS = ["tau_pass", "y_pass1", "y_pass2", "tables", "tau_transform", "adj_tau_pass", "adj_y_pass", "transport"]
 
 
@@ -98,6 +98,9 @@ def lib():
         L.kzk_set_tau_threads.argtypes = [vp, i32]
         L.kzk_get_tau_threads.argtypes = [vp]
         L.kzk_get_tau_threads.restype = i32
+        L.kzk_set_tau_fft_radix.argtypes = [vp, i32]
+        L.kzk_get_tau_fft_radix.argtypes = [vp]
+        L.kzk_get_tau_fft_radix.restype = i32
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -178,7 +181,7 @@ class Plan:
 
     def __init__(self, problems, dtype: str = "f64", stream=None, cfl_max: float = 1.0,
                  y_threads: Optional[int] = None, graph: bool = False, tau_threads: Optional[int] = None,
-                 state_fp64: bool = False):
+                 state_fp64: bool = False, tau_fft_radix: Optional[int] = None):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -197,6 +200,8 @@ class Plan:
             self.set_y_threads(y_threads)
         if tau_threads:
             self.set_tau_threads(tau_threads)
+        if tau_fft_radix:
+            self.set_tau_fft_radix(tau_fft_radix)
         if graph:
             self.set_graph(True)
 
@@ -232,9 +237,16 @@ class Plan:
     def tau_threads(self) -> int:
         return lib().kzk_get_tau_threads(self.h)
 
+    def set_tau_fft_radix(self, r: int):
+        _check(lib().kzk_set_tau_fft_radix(self.h, int(r)), "kzk_set_tau_fft_radix")
+
+    @property
+    def tau_fft_radix(self) -> int:
+        return lib().kzk_get_tau_fft_radix(self.h)
+
     def tuning(self) -> dict:
-        """The block sizes the plan runs with (y-pass and tau-pass)."""
-        return {"y_threads": self.y_threads, "tau_threads": self.tau_threads}
+        """The block sizes and the tau-transform radix schedule the plan runs with."""
+        return {"y_threads": self.y_threads, "tau_threads": self.tau_threads, "tau_fft_radix": self.tau_fft_radix}
 
 
     # -- buffers

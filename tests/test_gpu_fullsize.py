@@ -187,6 +187,67 @@ def test_autotune_picks_a_supported_size_and_keeps_results(torch_cuda, orc, dtyp
     assert rel_l2(plan.unpack(u)[0], orc.run(p)) < TOL[dtype]
 
 
+def test_autotune_cache_stores_and_reuses_the_choice(torch_cuda, orc, tmp_path, monkeypatch):
+    """KZK_TUNE_CACHE: a timed result is appended as one line (key, y-pass
+    threads, tau-pass threads, tau radix schedule, ms); a plan with the same
+    key takes the last stored choice without timing."""
+    from paper_2103_06080_amd import kzk
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("KZK_TUNE_CACHE", str(cache))
+    p = I.c1(n_steps=6)
+    plan = kzk.Plan(p, dtype="f32")
+    u = plan.pack([p.u0])
+    best = plan.autotune(u, 2)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    key, yt, tt, rx, ms = lines[0].split(" ")
+    assert key.startswith("kzk2|") and (int(yt), int(tt), int(rx)) == tuple(plan.tuning().values())
+    assert int(yt) == best and int(rx) in (8, 16) and float(ms) > 0
+    plan.close()
+    # a stored line for the same key wins (the last one), with no new timing
+    with open(cache, "a") as f:
+        f.write("%s 256 512 8 0.0100\n" % key)
+    plan = kzk.Plan(p, dtype="f32")
+    assert plan.autotune(u, 2) == 256
+    assert plan.tuning() == {"y_threads": 256, "tau_threads": 512, "tau_fft_radix": 8}
+    assert len(cache.read_text().splitlines()) == 2
+    plan.step(u, 0, 6)
+    assert plan.poll() == 0
+    assert rel_l2(plan.unpack(u)[0], orc.run(p)) < TOL["f32"]
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt,ny,tt", [(32, 64, 256), (64, 16, 256), (256, 128, 256), (2048, 64, 256),
+                                      (8192, 16, 256), (1024, 1024, 512), (4096, 32, 512)])
+def test_radix8_schedule_matches_radix16_and_oracle(torch_cuda, orc, dtype, nt, ny, tt):
+    """The radix-8 tau-transform schedule (kzk_set_tau_fft_radix(8)) on every
+    stage shape (tails of radix 2 and 4, the 2^12 = 8^4 transform, the
+    progression-indexed pre/post-processing at 1024 x 1024, 512-thread blocks
+    in FP32): the same march as the radix-16 schedule up to rounding, and the
+    oracle's within the bars."""
+    from paper_2103_06080_amd import kzk
+    if dtype == "f64":
+        tt = 256
+    p = I.c1(n_steps=4)
+    p = I.Problem(**{**p.__dict__, "n_tau": nt, "n_y": ny, "L_tau": 8.0, "tau0": -4.0, "h": 2e-4})
+    rng = I.SplitMix64(11)
+    T, a, modes = I._draw_nwave(rng)
+    p.u0 = I.nwave(p.tau(), p.y(), T, a, 0.2, modes, p.y0, p.L_y)
+    out = {}
+    for r in (16, 8):
+        plan = kzk.Plan(p, dtype=dtype, tau_threads=tt, tau_fft_radix=r)
+        assert plan.tau_fft_radix == r
+        u = plan.pack([p.u0])
+        plan.step(u, 0, p.n_steps)
+        assert plan.poll() == 0
+        out[r] = plan.unpack(u)[0]
+        plan.close()
+    ref = orc.run(p)
+    assert rel_l2(out[8], out[16]) < (1e-14 if dtype == "f64" else 2e-6)
+    assert rel_l2(out[8], ref) < TOL[dtype]
+
+
 def test_profile_sampling_counts_launches(torch_cuda):
     """kzk_profile_enable(k): the launches of every k-th step are bracketed
     (and the march's result does not depend on it)."""
