@@ -216,9 +216,15 @@ def side_measurements(args, value_fp32, ms_fp32):
         lam = torch.ones_like(u0)
         plan.adjoint(u0, lam, 0, q.n_steps, inputs.C5_CKPT)
         ta = _time(lambda: plan.adjoint(u0, lam, 0, q.n_steps, inputs.C5_CKPT), sync)
+        # one segment (checkpoint interval = the march): every stage input is
+        # stored during the forward sweep (2 n_steps fields), nothing is recomputed
+        plan.adjoint(u0, lam, 0, q.n_steps, q.n_steps)
+        tall = _time(lambda: plan.adjoint(u0, lam, 0, q.n_steps, q.n_steps), sync)
         assert plan.poll() == 0
         out["adjoint_c5_" + dt] = {"fwd_s": tf, "adjoint_s": ta, "adjoint_over_fwd": ta / tf,
-                                   "ckpt_every": inputs.C5_CKPT, "cache_assisted": True}
+                                   "ckpt_every": inputs.C5_CKPT, "cache_assisted": True,
+                                   "store_all": {"adjoint_s": tall, "adjoint_over_fwd": tall / tf,
+                                                 "stored_bytes": 2 * q.n_steps * q.points * (4 if dt == "f32" else 8)}}
         progress("adjoint %s done" % dt)
         plan.close()
         del plan
