@@ -283,12 +283,12 @@ def linear_march_error(state_fp64):
 
 # Table 2 of the paper, CUDA FP32 column (Titan V), seconds for the whole run of
 # each set on its own grid (N_theta = 7 * 2^k): context, not a target
-PAPER_CUDA_FP32_S = {1: 0.5564, 2: 3.788, 3: 28.31}
+PAPER_CUDA_FP32_S = {1: 0.5564, 2: 3.788, 3: 28.31, 4: 392.7}
 
 
 def paper_sets():
     """The paper's workload (full b with transport by the random medium,
-    regularised multiplier) on the grids of sets 1-3 (n_tau = N_theta = 7 2^k,
+    regularised multiplier) on the grids of sets 1-4 (n_tau = N_theta = 7 2^k,
     n_y the power of two nearest N_rho) and on the power-of-two grids nearest
     them ("_pow2"), each run for its N_sigma steps in FP32 with per-kernel
     events on every 8th step.  value: grid-point-steps/s; paper_value: the
@@ -296,7 +296,7 @@ def paper_sets():
     import torch
     from paper_2103_06080_amd import inputs, kzk
     res = {}
-    for k, pow2 in ((1, False), (2, False), (3, False), (1, True), (2, True), (3, True)):
+    for k, pow2 in ((1, False), (2, False), (3, False), (4, False), (1, True), (2, True), (3, True), (4, True)):
         p = inputs.paper_set(k, pow2=pow2)
         plan = kzk.Plan(p, dtype="f32")
         u0 = plan.pack([p.u0])

@@ -56,10 +56,13 @@ typedef enum {
 typedef enum { KZK_F32 = 0, KZK_F64 = 1 } kzk_dtype;
 
 typedef struct {
-    int32_t n_tau, n_y;     /* n_y a power of two in [16, 4096]; n_tau a power of two in
+    int32_t n_tau, n_y;     /* n_y a power of two in [16, 8192]; n_tau a power of two in
                                [32, 8192], or 7 * 2^k in [224, 7168] (the grids of Sec. 4,
                                N_theta = 7 * 2^k: a radix-7 stage in the tau-transform;
-                               then every solve of the plan has the same n_tau)          */
+                               then every solve of the plan has the same n_tau).  With
+                               n_y = 8192 the plan needs y-pass blocks of 512 or more
+                               threads and full column tiles in every solve
+                               (KZK_ERR_SIZE otherwise); no adjoint               */
     double tau0, L_tau;     /* periodic tau box [tau0, tau0 + L_tau)                      */
     double y0, L_y;         /* periodic y box [y0, y0 + L_y)                              */
     double x0, h;           /* marching origin and step: x_n = x0 + n h (paper: Delta sigma) */
@@ -135,7 +138,8 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
  * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
  * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0,
- * state_fp64 0 in FP32) on power-of-two n_tau; KZK_ERR_ARG otherwise. */
+ * state_fp64 0 in FP32) on power-of-two n_tau and n_y <= 4096; KZK_ERR_ARG
+ * otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 
@@ -157,7 +161,9 @@ kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
 
 /* Select the y-pass block size (256, 512 or 1024 threads; 1024 in FP32
  * only); rebuilds the tiled multiplier tables.  0 restores the default: the
- * smallest size whose column tiles are at least 32 bytes wide. */
+ * smallest size whose column tiles are at least 32 bytes wide.  KZK_ERR_ARG
+ * if 16 * threads < n_y of some solve; KZK_ERR_SIZE (plan unchanged) for a
+ * size that leaves a solve with n_y = 8192 without full column tiles. */
 kzk_status kzk_set_y_threads(kzk_plan *plan, int32_t threads);
 
 /* Select the tau-pass block size: 256 threads (one 8192-point line per

@@ -53,6 +53,7 @@ struct kzk_plan {
     int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
     int gk = 0;                           // > 0: every instance has M = 7 * 2^gk (mixed-radix tau-pass)
     int y_full = 0;                       // every instance has W n_y = 16 y_threads and n_y >= 512 (full y tiles)
+    int max_ny = 0;                       // largest n_y of the plan (8192 needs full tiles of 512+ threads)
     bool any_D_sched = false;
     int scheme = 0;                       // 0: ExpRK22, 1: exponential Euler (every solve)
     bool any_reg = false;                 // some solve uses the regularised multiplier
@@ -172,7 +173,7 @@ struct ProfScope {
 
 kzk_status check_params(const kzk_params& q) {
     if ((!pow2(q.n_tau) && !gen_k(q.n_tau)) || !pow2(q.n_y)) return KZK_ERR_SIZE;
-    if (q.n_tau < 32 || q.n_tau > 8192 || q.n_y < 16 || q.n_y > 4096) return KZK_ERR_SIZE;
+    if (q.n_tau < 32 || q.n_tau > 8192 || q.n_y < 16 || q.n_y > 8192) return KZK_ERR_SIZE;
     if (!(q.L_tau > 0) || !(q.L_y > 0) || !(q.h > 0) || !std::isfinite(q.h)) return KZK_ERR_ARG;
     if (q.dtype != KZK_F32 && q.dtype != KZK_F64) return KZK_ERR_ARG;
     if (!(q.A >= 0) || !std::isfinite(q.A) || !std::isfinite(q.D) || !std::isfinite(q.nl)) return KZK_ERR_ARG;
@@ -204,7 +205,7 @@ int default_y_threads(const kzk_plan* p) {
     const int cands[3] = {256, 512, 1024};
     int last = 0;
     for (int nt : cands) {
-        if (!kzk::y_threads_supported(p->dtype == KZK_F64, nt)) continue;
+        if (!kzk::y_threads_supported(p->dtype == KZK_F64, nt) || nt * 16 < p->max_ny) continue;
         last = nt;
         bool wide = true;
         for (const InstDesc& d : p->desc) {
@@ -304,7 +305,12 @@ kzk_status layout(kzk_plan* p) {
         if (d.M / 16 < d.W || d.M < 256) p->tau_prog = 0;
     p->y_full = 1;
     for (const InstDesc& d : p->desc)
-        if (d.W * d.n_y != 16 * p->y_threads || d.n_y < 512) p->y_full = 0;
+        if (d.W < 1 || d.W * d.n_y != 16 * p->y_threads || d.n_y < 512) p->y_full = 0;
+    // 8192-row columns: full tiles only, in the variant that loads their twiddles per stage
+    if (p->max_ny > 4096) {
+        if (!p->y_full) return KZK_ERR_SIZE;
+        p->y_full = 2;
+    }
     p->y_grid = kzk::y_resident_blocks(p->dtype == KZK_F64, p->s64, p->y_threads, p->y_full, p->device);
     if (p->y_grid <= 0) return KZK_ERR_DEVICE;
     if (hipMemcpy(p->dDesc, p->desc.data(), sizeof(InstDesc) * p->n_inst, hipMemcpyHostToDevice) != hipSuccess ||
@@ -539,6 +545,7 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
         std::memset(&d, 0, sizeof(d));
         d.n_tau = q.n_tau;
         d.n_y = q.n_y;
+        p->max_ny = std::max(p->max_ny, q.n_y);
         d.M = q.n_tau / 2;
         d.Nh = q.n_y / 2 + 1;
         d.off_state = (long long)so;
@@ -759,11 +766,18 @@ kzk_status kzk_set_y_threads(kzk_plan* p, int32_t threads) {
     if (!p) return KZK_ERR_ARG;
     if (threads == 0) threads = default_y_threads(p);
     if (!kzk::y_threads_supported(p->dtype == KZK_F64, threads)) return KZK_ERR_ARG;
+    if (threads * 16 < p->max_ny) return KZK_ERR_ARG;   // a column tile holds at least one column
     if (hipStreamSynchronize(p->stream) != hipSuccess) return KZK_ERR_DEVICE;
     drop_graph(p);
+    const int old = p->y_threads;
     p->y_threads = threads;
     kzk_status st = layout(p);
-    if (st != KZK_OK) return st;
+    if (st != KZK_OK) {
+        // not a layout this plan can take (8192-row columns without full tiles): keep the previous one
+        p->y_threads = old;
+        if (layout(p) != KZK_OK) return KZK_ERR_STATE;
+        return st;
+    }
     st = build_tables(p, 0, false);
     if (st != KZK_OK) return st;
     return hipStreamSynchronize(p->stream) == hipSuccess ? KZK_OK : KZK_ERR_DEVICE;
@@ -1008,8 +1022,11 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
     const bool prof = p->prof;
     p->prof = false;
     for (int c : ycands) {
-        if (!kzk::y_threads_supported(p->dtype == KZK_F64, c)) continue;
-        if ((st = kzk_set_y_threads(p, c)) != KZK_OK) break;
+        if (!kzk::y_threads_supported(p->dtype == KZK_F64, c) || c * 16 < p->max_ny) continue;
+        if ((st = kzk_set_y_threads(p, c)) != KZK_OK) {
+            if (st == KZK_ERR_SIZE) { st = KZK_OK; continue; }   // a layout this plan cannot take
+            break;
+        }
         for (int t : tcands) {
             if (!tau_ok(t)) continue;
             if ((st = kzk_set_tau_threads(p, t)) != KZK_OK) break;
@@ -1048,7 +1065,7 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
     // ExpRK22, zeroed mean, Burgers b, state in the working precision
-    if (p->scheme != 0 || p->any_reg || p->transport || p->s64 || p->gk) return KZK_ERR_ARG;
+    if (p->scheme != 0 || p->any_reg || p->transport || p->s64 || p->gk || p->max_ny > 4096) return KZK_ERR_ARG;
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

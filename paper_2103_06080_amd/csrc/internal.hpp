@@ -73,8 +73,9 @@ bool tau_threads_supported(int dtype_is_f64, int nt);
 // y-pass over n_items column tiles with at most max_blocks persistent blocks
 // (0: one block per tile).  step: index into the D schedule of instances
 // whose multipliers the y-pass computes itself (those with D_step; stage 1
-// then writes their h Phi2 table for stage 2).  full: every instance has
-// W n_y = 16 nt and n_y >= 512 (full tiles; progression addressing).
+// then writes their h Phi2 table for stage 2).  full: 1 if every instance
+// has W n_y = 16 nt and n_y >= 512 (full tiles; progression addressing), 2
+// if so and some instance has n_y = 8192 (nt >= 512), else 0.
 // By: tau-spectrum of the transverse transport part of b (instances with
 // vel = 1; nullptr otherwise), added to sigma_m B before the y-transform.
 // s64: an FP32 plan whose spectral state U and stage value P are FP64.
@@ -95,7 +96,7 @@ hipError_t launch_yweno(const InstDesc* d_desc, const YwItem* d_items, int n_ite
 // phase (modes[5][n_modes]).
 hipError_t launch_velocity(const InstDesc* d_desc, int inst, const double* modes, int n_modes, double x0, double h,
                            int n_nodes, double* tab, double* amax, hipStream_t s);
-// blocks of the y-pass kernels (block size nt, full-tile variant or not)
+// blocks of the y-pass kernels (block size nt, full as for launch_y)
 // resident at once on the device
 int y_resident_blocks(int dtype_is_f64, int s64, int nt, int full, int device);
 

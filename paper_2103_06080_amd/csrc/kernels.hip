@@ -859,11 +859,11 @@ __global__ __launch_bounds__(256) void velocity_max_kernel(const InstDesc* __res
 // C~* + i P backward.  One block per instance; the FFT runs on the first
 // n_y/16 threads.
 template <typename T, int STAGE>
-__global__ __launch_bounds__(256) void dc_kernel(const InstDesc* __restrict__ descs, cpx<T>* __restrict__ C,
+__global__ __launch_bounds__(512) void dc_kernel(const InstDesc* __restrict__ descs, cpx<T>* __restrict__ C,
                                                  cpx<T>* __restrict__ P, cpx<T>* __restrict__ U,
                                                  const cpx<T>* __restrict__ By, const cpx<T>* __restrict__ twst,
                                                  int step) {
-    __shared__ alignas(32) cpx<T> lds[padded(4096)];
+    __shared__ alignas(32) cpx<T> lds[padded(8192)];
     const InstDesc& d = descs[blockIdx.x];
     if (!(d.reg_eps > 0.0)) return;
     const bool tb = d.vel != 0 && By != nullptr;
@@ -1016,7 +1016,12 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // in FP32 plans that keep their state in FP64: the combine then runs in FP64
 // with the step's multipliers evaluated in FP64, and only the inputs of the
 // inverse y-transform are rounded to T).
-template <typename T, int NT, int STAGE, bool FULL, typename S = T>
+//
+// BIG (full tiles only): some instance has n_y = 8192, whose column
+// transform has three stages with twiddles, more than the registers hold
+// beside the tile: this variant loads the twiddles of every column transform
+// per stage (look-ahead) instead of holding them.
+template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool BIG = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
         const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<S>* __restrict__ P, cpx<S>* __restrict__ U,
@@ -1099,7 +1104,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         }
     }
     if (Ny != tw_ny) {
-        lds_fft_twiddles<T>(Ny, ft, twst, ytw);
+        if constexpr (!BIG) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
         tw_ny = Ny;
     }
     if constexpr (FULL) {
@@ -1110,7 +1115,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     }
     __syncthreads();
     if (STAGE == 0) {
-        lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
+        if constexpr (BIG) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
+        else lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
         if constexpr (FULL) {
             const auto rc = buf_rsrc(Ct), ru = buf_rsrc(Ut);
             #pragma unroll
@@ -1128,7 +1134,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         continue;
     }
 
-    lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
+    if constexpr (BIG) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
+    else lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
     // indices n and Ny - n.  A thread has at most 9 half-tile items
     // (Nh * W <= 8 NT + W); their global loads are issued before use.
@@ -1344,7 +1351,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     }
     }
     __syncthreads();
-    lds_fft_held<T, 1>(fbuf, fbase, Ny, ft, act, ytw);
+    if constexpr (BIG) lds_fft<T, 1>(fbuf, fbase, Ny, ft, act, twst);
+    else lds_fft_held<T, 1>(fbuf, fbase, Ny, ft, act, ytw);
     if constexpr (FULL) {
         const auto rc = buf_rsrc(Ct);
         // an opaque copy of the base slot, so that the compiler recomputes the
@@ -1854,7 +1862,7 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NT, bool FULL, typename S>
+template <typename T, int NT, bool FULL, typename S, bool BIG>
 static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
                                void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
                                int step, hipStream_t s) {
@@ -1867,42 +1875,49 @@ static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     return hipGetLastError();
 }
 
 // s64: FP32 plan with the state in FP64
-template <typename T, int NT, bool FULL>
+template <typename T, int NT, bool FULL, bool BIG>
 static hipError_t launch_y_nt(int stage, int s64, const InstDesc* d_desc, const YItem* d_items, int n_items,
                               int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                               const void* twst, int step, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         if (s64)
-            return launch_y_nts<T, NT, FULL, double>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
-                                                     tabs, twst, step, s);
+            return launch_y_nts<T, NT, FULL, double, BIG>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+                                                          U, tabs, twst, step, s);
     }
-    return launch_y_nts<T, NT, FULL, T>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst, step,
-                                        s);
+    return launch_y_nts<T, NT, FULL, T, BIG>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+                                             step, s);
 }
 
+// full: 0 general tiles, 1 full tiles, 2 full tiles with an 8192-row instance
 template <typename T, int NT, typename S>
-static int y_resident_nt(int device, bool full) {
+static int y_resident_nt(int device, int full) {
     int ncu = 0, per = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
         return 0;
     int lo = 1 << 30;
-    const void* fns[2][3] = {{(const void*)y_kernel<T, NT, 0, false, S>, (const void*)y_kernel<T, NT, 1, false, S>,
+    // the 8192-row variant exists for blocks of 512 and 1024 threads only
+    constexpr bool big = NT >= 512;
+    const void* fns[3][3] = {{(const void*)y_kernel<T, NT, 0, false, S>, (const void*)y_kernel<T, NT, 1, false, S>,
                               (const void*)y_kernel<T, NT, 2, false, S>},
                              {(const void*)y_kernel<T, NT, 0, true, S>, (const void*)y_kernel<T, NT, 1, true, S>,
-                              (const void*)y_kernel<T, NT, 2, true, S>}};
-    for (const void* f : fns[full ? 1 : 0]) {
+                              (const void*)y_kernel<T, NT, 2, true, S>},
+                             {(const void*)y_kernel<T, NT, 0, true, S, big>,
+                              (const void*)y_kernel<T, NT, 1, true, S, big>,
+                              (const void*)y_kernel<T, NT, 2, true, S, big>}};
+    if (full < 0 || full > 2 || (full == 2 && !big)) return 0;
+    for (const void* f : fns[full]) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, NT, 0) != hipSuccess || per <= 0) return 0;
         lo = per < lo ? per : lo;
     }
@@ -1931,21 +1946,23 @@ bool y_threads_supported(int is_f64, int nt) {
     return nt == 1024 && !is_f64;
 }
 
-template <typename T, bool FULL>
+template <typename T, bool FULL, bool BIG>
 static hipError_t launch_y_full(int stage, int s64, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
                                 int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                                 const void* twst, int step, hipStream_t s) {
     switch (nt) {
     case 256:
-        return launch_y_nt<T, 256, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                         step, s);
+        if constexpr (!BIG)
+            return launch_y_nt<T, 256, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                                  tabs, twst, step, s);
+        return hipErrorInvalidValue;
     case 512:
-        return launch_y_nt<T, 512, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                         step, s);
+        return launch_y_nt<T, 512, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+                                              twst, step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024, FULL>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
-                                              twst, step, s);
+            return launch_y_nt<T, 1024, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                                   tabs, twst, step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -1956,10 +1973,13 @@ hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc
                     int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                     const void* twst, int step, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    return full ? launch_y_full<T, true>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
-                                         twst, step, s)
-                : launch_y_full<T, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
-                                          twst, step, s);
+    if (full == 2)
+        return launch_y_full<T, true, true>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                            tabs, twst, step, s);
+    return full ? launch_y_full<T, true, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                                tabs, twst, step, s)
+                : launch_y_full<T, false, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+                                                 U, tabs, twst, step, s);
 }
 
 // b^ = sigma F^ in place on one instance's tiled tau-spectrum (element e of
@@ -1999,9 +2019,9 @@ hipError_t launch_dc(int stage, const InstDesc* d_desc, int n_inst, void* C, voi
     const cpx<T>* b = static_cast<const cpx<T>*>(By);
     const cpx<T>* w = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((dc_kernel<T, 1>), dim3(n_inst), dim3(256), 0, s, d_desc, c, p, u, b, w, step);
+        hipLaunchKernelGGL((dc_kernel<T, 1>), dim3(n_inst), dim3(512), 0, s, d_desc, c, p, u, b, w, step);
     else
-        hipLaunchKernelGGL((dc_kernel<T, 2>), dim3(n_inst), dim3(256), 0, s, d_desc, c, p, u, b, w, step);
+        hipLaunchKernelGGL((dc_kernel<T, 2>), dim3(n_inst), dim3(512), 0, s, d_desc, c, p, u, b, w, step);
     return hipGetLastError();
 }
 
@@ -2016,8 +2036,8 @@ hipError_t launch_yweno(const InstDesc* d_desc, const YwItem* d_items, int n_ite
 hipError_t launch_velocity(const InstDesc* d_desc, int inst, const double* modes, int n_modes, double x0, double h,
                            int n_nodes, double* tab, double* amax, hipStream_t s) {
     if (n_nodes <= 0) return hipSuccess;
-    // the host passes n_y through the descriptor; 4096 rows at most
-    hipLaunchKernelGGL(velocity_kernel, dim3(16, n_nodes), dim3(256), 0, s, d_desc, inst, modes, n_modes, x0, h, tab);
+    // the host passes n_y through the descriptor; 8192 rows at most
+    hipLaunchKernelGGL(velocity_kernel, dim3(32, n_nodes), dim3(256), 0, s, d_desc, inst, modes, n_modes, x0, h, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(velocity_max_kernel, dim3(n_nodes), dim3(256), 0, s, d_desc, inst, tab, amax);

@@ -266,12 +266,11 @@ def medium(seed: int, n_modes: int = 200) -> dict:
 
 # Table 0 of the paper (N_sigma, N_rho, N_theta) and the grids used for them
 # here (n_tau x n_y = theta x rho): n_tau = N_theta itself (7 * 2^k), n_y the
-# power of two nearest N_rho (the y-transform takes powers of two; set 4's
-# 10000 rows would need 8192, above the 4096-row limit); the power-of-two
-# grids nearest both are kept as a second stand-in
+# power of two nearest N_rho (the y-transform takes powers of two); the
+# power-of-two grids nearest both are kept as a second stand-in
 PAPER_SETS = {1: (300, 1250, 448), 2: (600, 2500, 896), 3: (1200, 5000, 1792), 4: (2400, 10000, 3584)}
-PAPER_SET_GRIDS = {1: (448, 1024), 2: (896, 2048), 3: (1792, 4096)}
-PAPER_SET_POW2_GRIDS = {1: (512, 1024), 2: (1024, 2048), 3: (2048, 4096)}
+PAPER_SET_GRIDS = {1: (448, 1024), 2: (896, 2048), 3: (1792, 4096), 4: (3584, 8192)}
+PAPER_SET_POW2_GRIDS = {1: (512, 1024), 2: (1024, 2048), 3: (2048, 4096), 4: (4096, 8192)}
 
 
 def paper_set(k: int, seed: int = 0, n_modes: int = 200, reg_eps: float = 2.0 ** -24,

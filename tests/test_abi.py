@@ -53,7 +53,7 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n_tau=48), 2), (dict(n_tau=16), 2), (dict(n_tau=16384), 2), (dict(n_y=8), 2), (dict(n_y=8192), 2),
+    (dict(n_tau=48), 2), (dict(n_tau=16), 2), (dict(n_tau=16384), 2), (dict(n_y=8), 2), (dict(n_y=16384), 2),
     (dict(n_tau=112), 2), (dict(n_tau=14336), 2), (dict(n_tau=96), 2), (dict(n_tau=480), 2), (dict(n_y=448), 2),
     (dict(h=0.0), 1), (dict(h=-1.0), 1), (dict(L_tau=0.0), 1), (dict(dtype=3), 1), (dict(A=-1.0), 1),
     (dict(weno_eps=0.0), 1), (dict(lf_scope=1), 1), (dict(cfl_max=-1.0), 1),

@@ -221,3 +221,94 @@ def test_set3_grid_full_march_of_y_independent_field_matches_oracle_line(torch_c
     err = max(rel_l2(got[j], ref) for j in (0, 1234, p.n_y - 1))
     print("set 3 grid y-independent 1200-step march %s: rel l2 %.3e" % (dtype, err))
     assert err < bar, err
+
+
+# ---- 8192 rows (set 4 of Table 0: N_rho = 10000 -> n_y = 8192)
+
+@pytest.mark.parametrize("dtype,yt", [("f64", 512), ("f32", 1024), ("f32", 512)])
+@pytest.mark.parametrize("nt", [32, 448])
+def test_march_with_8192_rows_matches_oracle(torch_cuda, orc, dtype, yt, nt):
+    """Column transforms of 8192 points (twiddles loaded per stage) in the
+    full-tile y-passes of 1 or 2 columns, with coefficient schedules."""
+    p = small(nt, 8192, n_steps=3, A=1e-4)
+    p.D_step = 0.05 * (1.0 + 0.3 * np.sin(1.0 + np.arange(p.n_steps)))
+    p = dataclasses.replace(p, D_const=None)
+    got = march(p, dtype, y_threads=yt)
+    ref = orc.run(p)
+    err = rel_l2(got, ref)
+    print("8192 rows %s %d x 8192 (%d threads): rel l2 %.2e" % (dtype, nt, yt, err))
+    assert err < TOL[dtype], err
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_transport_with_8192_rows_matches_oracle(torch_cuda, orc, dtype):
+    """The full b and the regularised multiplier (mean column transformed along
+    8192 rows) on a 64 x 8192 grid."""
+    eps = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}[dtype]
+    p = I.Problem(name="m", n_tau=64, n_y=8192, h=2e-3, n_steps=3, D_step=np.full(3, 0.05),
+                  nl_node=np.full(4, 0.9), u0=np.zeros((8192, 64)), A=1e-4, D_const=0.05, nl_const=0.9,
+                  x0=1.5, L_y=400.0, y0=0.0, reg_eps=eps, **I.medium(9, 200))
+    rng = I.SplitMix64(9)
+    T, a, modes = I._draw_nwave(rng)
+    p.u0 = I.nwave(p.tau(), p.y(), T, a, 0.1, modes, p.y0, p.L_y) + 0.1
+    got = march(p, dtype)
+    ref = orc.run(p)
+    err = rel_l2(got, ref)
+    print("8192 rows transport %s: rel l2 %.2e" % (dtype, err))
+    assert err < TOL[dtype], err
+
+
+def test_8192_rows_need_full_tiles_of_512_threads(torch_cuda):
+    from paper_2103_06080_amd import kzk
+    p = small(32, 8192, n_steps=2)
+    plan = kzk.Plan(p, dtype="f32")
+    assert plan.y_threads == 1024
+    with pytest.raises(kzk.KZKError):
+        plan.set_y_threads(256)
+    plan.set_y_threads(512)
+    assert plan.y_threads == 512
+    u = plan.pack([p.u0])
+    with pytest.raises(kzk.KZKError):
+        plan.adjoint(u, u.clone(), 0, 2, ckpt=1)
+    plan.close()
+    # a solve with few rows next to the 8192-row one leaves no full-tile layout
+    with pytest.raises(kzk.KZKError):
+        kzk.Plan([small(448, 8192, n_steps=2), small(448, 64, n_steps=2)], dtype="f32")
+
+
+@pytest.mark.parametrize("dtype,state64,bar", [("f64", False, 1e-11), ("f32", True, 2e-5)])
+def test_set4_grid_full_linear_march_matches_closed_form(torch_cuda, dtype, state64, bar):
+    """Set 4's grid (3584 x 8192) and coefficients over its 2400 steps
+    (Sigma = 120), nonlinear term and medium off, against the closed form."""
+    q = I.paper_set(4)
+    p = I.Problem(name="set4-linear", n_tau=q.n_tau, n_y=q.n_y, h=q.h, n_steps=q.n_steps, D_step=q.D_step,
+                  nl_node=np.zeros_like(q.nl_node), u0=q.u0, tau0=q.tau0, L_tau=q.L_tau, y0=q.y0, L_y=q.L_y,
+                  A=q.A, D_const=q.D_const, nl_const=0.0)
+    tau, y = p.tau(), p.y()
+    k, s, yc = 2 * math.pi * 5 / p.L_tau, 12.0, 200.0
+    p.u0 = np.cos(k * tau)[None, :] * np.exp(-(y - yc) ** 2 / (2 * s * s))[:, None]
+    X = p.h * p.n_steps
+    c = s * s - 1j * float(p.h * p.D_step.sum()) / k
+    ref = math.exp(-p.A * k * k * X) * np.real(
+        np.exp(1j * k * tau)[None, :] * (s / np.sqrt(c)) * np.exp(-(y - yc) ** 2 / (2 * c))[:, None])
+    kw = {"state_fp64": True} if state64 else {}
+    err = rel_l2(march(p, dtype, **kw), ref)
+    print("set 4 grid (3584 x 8192) linear 2400-step march %s: rel l2 %.3e" % (dtype, err))
+    assert err < bar, err
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-11), ("f32", 1e-4)])
+def test_set4_grid_full_march_of_y_independent_field_matches_oracle_line(torch_cuda, orc, dtype, bar):
+    """Set 4's grid, coefficients, regularised multiplier and N-wave without
+    the medium: all 2400 steps against the oracle's single line."""
+    eps = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}[dtype]
+    q = I.paper_set(4, reg_eps=eps)
+    p = I.Problem(name="set4-line", n_tau=q.n_tau, n_y=q.n_y, h=q.h, n_steps=q.n_steps, D_step=q.D_step,
+                  nl_node=q.nl_node, u0=q.u0, tau0=q.tau0, L_tau=q.L_tau, y0=q.y0, L_y=q.L_y, A=q.A,
+                  D_const=q.D_const, nl_const=q.nl_const, reg_eps=eps)
+    line = dataclasses.replace(p, n_y=1, u0=p.u0[:1].copy())
+    ref = orc.run(line)[0]
+    got = march(p, dtype)
+    err = max(rel_l2(got[j], ref) for j in (0, 4321, p.n_y - 1))
+    print("set 4 grid y-independent 2400-step march %s: rel l2 %.3e" % (dtype, err))
+    assert err < bar, err
