@@ -141,6 +141,26 @@ def sampled_march_error(name, u_host, n_steps):
             "max_err_over_max_u": float(np.abs(got - ref).max() / np.abs(ref).max())}
 
 
+def measured_copy_gbs(mib=1024, reps=5):
+    """Device-to-device copy bandwidth (bytes read + written per second) of a
+    mib-MiB buffer, the best of reps copies timed with events."""
+    import torch
+    src = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * mib * (1 << 20) / best / 1e9
+
+
 def _time(fn, sync):
     sync()
     t0 = time.perf_counter()
@@ -442,6 +462,11 @@ def main():
         roofline["step_model_11_gbs"] = round(11 * step_bytes / elapsed / 1e9, 1)
         roofline["step_model_11_frac"] = round(11 * step_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4)
         roofline["step_model_12_gbs"] = round(12 * step_bytes / elapsed / 1e9, 1)
+        # the same fractions against a measured device copy (1 GiB read + 1 GiB written)
+        cp = measured_copy_gbs()
+        roofline["measured_copy_gbs"] = round(cp, 1)
+        roofline["hbm_frac_of_copy"] = round(gbs / cp, 4)
+        roofline["step_model_11_frac_of_copy"] = round(11 * step_bytes / elapsed / 1e9 / cp, 4)
 
     tuning = plan.tuning()
     errors = {"full_march_sampled_rows": sampled_march_error(args.config, u_host, steps_per_march)}

@@ -312,3 +312,18 @@ def test_set4_grid_full_march_of_y_independent_field_matches_oracle_line(torch_c
     err = max(rel_l2(got[j], ref) for j in (0, 4321, p.n_y - 1))
     print("set 4 grid y-independent 2400-step march %s: rel l2 %.3e" % (dtype, err))
     assert err < bar, err
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-12), ("f32", 1e-4)])
+def test_largest_grid_march_of_y_independent_field_matches_oracle_line(torch_cuda, orc, dtype, bar):
+    """The largest supported grid, 8192 x 8192 (both transforms at their
+    maximum length, 8192-row columns in full tiles), 20 steps of a nonlinear,
+    absorbing march of a y-independent N-wave against the oracle's line."""
+    p = small(8192, 8192, n_steps=20, h=2e-4, A=1e-4)
+    p.u0 = np.tile(p.u0[:1], (8192, 1))
+    line = dataclasses.replace(p, n_y=1, u0=p.u0[:1].copy())
+    ref = orc.run(line)[0]
+    got = march(p, dtype)
+    err = max(rel_l2(got[j], ref) for j in (0, 5000, 8191))
+    print("8192 x 8192 y-independent 20-step march %s: rel l2 %.2e" % (dtype, err))
+    assert err < bar, err
