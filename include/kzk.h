@@ -136,7 +136,11 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * march, derived from Sec. 3.3 eq. (19)): given the field u0_dev at step
  * first_step and lam_dev = dL/du at step first_step + n_steps, write dL/du0
  * into grad_dev (may alias lam_dev).  The forward march is recomputed from
- * checkpoints taken every ckpt_every steps.  Asynchronous.  For ExpRK22
+ * checkpoints taken every ckpt_every steps; the stage inputs of one interval
+ * (2 ckpt_every fields) are stored, so ckpt_every >= n_steps recomputes
+ * nothing.  ckpt_every = 0: the longest interval (halving from n_steps)
+ * whose stored fields and checkpoints fit in half of the device memory free
+ * at the call.  Asynchronous; the result does not depend on the interval.  For ExpRK22
  * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0,
  * state_fp64 0 in FP32) on power-of-two n_tau and n_y <= 4096; KZK_ERR_ARG
  * otherwise. */

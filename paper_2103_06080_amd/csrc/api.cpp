@@ -1063,7 +1063,7 @@ extern "C" int32_t kzk_autotune(kzk_plan* p, const void* u, int32_t n_trial) {
 
 extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, int32_t first, int32_t n,
                                   int32_t ckpt, void* grad) {
-    if (!p || !u0 || !lam || !grad || ckpt < 1) return KZK_ERR_ARG;
+    if (!p || !u0 || !lam || !grad || ckpt < 0) return KZK_ERR_ARG;
     // ExpRK22, zeroed mean, Burgers b, state in the working precision
     if (p->scheme != 0 || p->any_reg || p->transport || p->s64 || p->gk || p->max_ny > 4096) return KZK_ERR_ARG;
     kzk_status st = check_range(p, first, n);
@@ -1074,7 +1074,20 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
             return KZK_ERR_DEVICE;
         return KZK_OK;
     }
-    const int K = std::min<int>(ckpt, n);
+    int K = std::min<int>(ckpt, n);
+    if (ckpt == 0) {
+        // the longest checkpoint interval whose stored stage inputs (2 K fields)
+        // and checkpoints (2 spectral states per segment) fit in half of the
+        // device memory free now; K = n stores the whole march (no recomputation)
+        size_t fr = 0, total = 0;
+        if (hipMemGetInfo(&fr, &total) != hipSuccess) return KZK_ERR_DEVICE;
+        const size_t budget = fr / 2;
+        K = 1;
+        for (int k = n; k >= 1; k = k > 1 ? (k + 1) / 2 : 0) {
+            const size_t segs = (size_t)((n + k - 1) / k);
+            if (2 * (size_t)k * ub + 2 * segs * sb <= budget) { K = k; break; }
+        }
+    }
     const int nseg = (n + K - 1) / K;
     if ((st = adjoint_workspace(p, (size_t)K, (size_t)nseg)) != KZK_OK) return st;
     char* ck = (char*)p->dCk;

@@ -64,7 +64,8 @@ def test_adjoint_checkpoint_interval_does_not_change_result(torch_cuda):
     g1 = plan.unpack(plan.adjoint(u0, l, 0, 9, 1))[0]
     g9 = plan.unpack(plan.adjoint(u0, l, 0, 9, 9))[0]
     g4 = plan.unpack(plan.adjoint(u0, l, 0, 9, 4))[0]
-    assert np.array_equal(g1, g9) and np.array_equal(g1, g4)
+    g0 = plan.unpack(plan.adjoint(u0, l, 0, 9, 0))[0]     # interval chosen from the free memory
+    assert np.array_equal(g1, g9) and np.array_equal(g1, g4) and np.array_equal(g1, g0)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
