@@ -4,7 +4,9 @@ The gradient of any loss of the final field with respect to the initial
 field comes from the hand-written discrete adjoint of the whole march
 (transposed FFTs, conjugate multipliers, WENO5 weight Jacobians and the
 Lax-Friedrichs speed term), with checkpointed recomputation every `ckpt`
-steps.  Only the loss itself is differentiated by torch.
+steps (0: the longest interval whose stored fields fit in half of the free
+device memory, the whole march when it fits).  Only the loss itself is
+differentiated by torch.
 """
 from __future__ import annotations
 
