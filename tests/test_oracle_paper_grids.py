@@ -62,3 +62,16 @@ def test_exprk22_second_order_on_a_7_2k_grid(orc):
         sols.append(orc.run(p))
     p_obs = math.log2(np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2]))
     assert 1.9 <= p_obs <= 2.6, p_obs
+
+
+@pytest.mark.parametrize("m", [1, 3, 5, 9, 15])
+@pytest.mark.parametrize("a", [0, 1, 3, 5])
+def test_mixed_radix_fft_other_odd_factors_match_numpy(orc, m, a):
+    """Lengths 2^a m for odd m other than 7: the radix-2 steps down to the
+    odd factor and its direct sum, in both directions."""
+    n = m << a
+    x = I.random_field(100 + n, (n,)) + 1j * I.random_field(101 + n, (n,))
+    ref = np.fft.fft(x)
+    assert np.abs(orc.fft(x) - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    back = orc.fft(orc.fft(x), 1) / n
+    assert np.abs(back - x).max() < 1e-13 * np.abs(x).max()
