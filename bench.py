@@ -31,7 +31,7 @@ ALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # issue rate of the instructions this build uses (no packed FP32):
 # 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz, the same in FP32 and FP64
 NONPACKED_PEAK_TFLOPS = 78.6
-ORACLE_STEPS = 4               # steps of the oracle sample (CPU baseline and first-steps parity)
+ORACLE_STEPS = 8               # steps of the oracle sample (CPU baseline and first-steps parity)
 
 WORKLOADS = {
     # name: (builder, default dtype)
