@@ -100,7 +100,8 @@ typedef struct {
        |U~(K_n)| = sqrt(E(|K_n|)/N), E(K) = sigma_u^2 K^3 L^4 exp(-(K L/2)^2) / 8,
        normalised by vel_c0 (the paper: lambda = 6.86 m, sigma_u = 3 m/s,
        c0 = 343 m/s).  Needs 1 <= n_steps_max <= 65534 (the field is tabulated
-       at every node); the same vel for every solve of a plan.                    */
+       at the nodes 0 .. n_steps_max, with or without D_step / nl_node; steps
+       beyond them return KZK_ERR_STATE); the same vel for every solve of a plan. */
     int32_t vel;
     int32_t vel_modes;
     const double *vel_phi, *vel_theta;

@@ -580,7 +580,8 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
             p->any_D_sched = true;
         }
         if (q.nl_node) p->nlsched[i].assign(q.nl_node, q.nl_node + q.n_steps_max + 1);
-        if (q.D_step || q.nl_node) {
+        // the schedules, and with transport the velocity tables (nodes 0 .. n_steps_max), bound the steps
+        if (q.D_step || q.nl_node || q.vel == 1) {
             long long lim = q.n_steps_max;
             p->steps_limit = p->steps_limit < 0 ? lim : std::min(p->steps_limit, lim);
         }

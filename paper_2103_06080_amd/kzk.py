@@ -148,10 +148,9 @@ def make_params(p, dtype: int, cfl_max: float = 1.0, keep: Optional[list] = None
             keep += [a, b, D, nl]
         vphi = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         vtheta = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        if not nmax:   # the field is tabulated at the nodes of the schedule
-            D_ptr = D.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            nl_ptr = nl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            nmax = len(D)
+        # the field is tabulated at the nodes 0 .. n_steps_max; constant
+        # coefficients still go without schedules (multiplier tables built once)
+        nmax = max(nmax, len(D))
     return Params(p.n_tau, p.n_y, p.tau0, p.L_tau, p.y0, p.L_y, p.x0, p.h, dtype,
                   float(p.D_const if p.D_const is not None else 0.0), p.A,
                   float(p.nl_const if p.nl_const is not None else 0.0),

@@ -122,3 +122,20 @@ def test_paper_set1_matches_oracle(torch_cuda, orc, dtype, pow2):
     e2, em = rel_l2(got, ref), max_rel(got, ref)
     print("paper set 1 %dx%d %s, 6 steps: rel l2 %.2e max %.2e" % (p.n_tau, p.n_y, dtype, e2, em))
     assert e2 < TOL[dtype] and em < TOL[dtype], (e2, em)
+
+
+def test_transport_march_stays_within_the_tabulated_nodes(torch_cuda):
+    """With constant coefficients the plan gets no schedules (its multiplier
+    tables are built once) but the velocity field is tabulated at the nodes
+    0 .. n_steps: steps beyond them are refused (KZK_ERR_STATE), inside them
+    the march runs."""
+    from paper_2103_06080_amd import kzk
+    p = medium_case(64, 16, 3)
+    plan = kzk.Plan(p, dtype="f64")
+    u = plan.pack([p.u0])
+    with pytest.raises(kzk.KZKError) as e:
+        plan.step(u, 1, 3)
+    assert e.value.code == 7
+    plan.step(u, 0, 3)
+    assert plan.poll() == 0
+    plan.close()
