@@ -303,9 +303,11 @@ __device__ __forceinline__ void c2r_pre(const cpx<T>* __restrict__ X, SpecIdx ix
     }
 }
 
+// add: a spectrum in the same layout added to the result (nullptr: none).
 template <typename T>
 __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int M, int t,
-                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw) {
+                                         int tpr, const cpx<T>* __restrict__ tw, int log2_ntw,
+                                         const cpx<T>* __restrict__ add = nullptr) {
     const int sh = log2_ntw - ilog2(2 * M);
     const PairIdx pi{t, tpr, M, sh, ix};
     #pragma unroll
@@ -317,11 +319,12 @@ __device__ __forceinline__ void r2c_post(const cpx<T>* lds, int base, cpx<T>* __
         cpx<T> a, b;
         r2c_pair(zk, zm, tw[pi.w(q)], a, b);
         if (k == 0) {
-            X[0] = cpx<T>{a.x, b.x};   // slot 0 = (X_0, X_M) = (A - Q, A + Q) real parts
+            a = cpx<T>{a.x, b.x};   // slot 0 = (X_0, X_M) = (A - Q, A + Q) real parts
+            X[0] = add ? a + add[0] : a;
             continue;
         }
-        X[pi.xk(q)] = a;
-        if (2 * k != M) X[pi.xm(q)] = b;
+        X[pi.xk(q)] = add ? a + add[pi.xk(q)] : a;
+        if (2 * k != M) X[pi.xm(q)] = add ? b + add[pi.xm(q)] : b;
     }
 }
 
@@ -1439,9 +1442,12 @@ __device__ __forceinline__ void weno_face_grad(T v0, T v1, T v2, T v3, T v4, T e
     T A0 = v0 - (T)2 * v1 + v2, B0 = v0 - (T)4 * v1 + (T)3 * v2;
     T A1 = v1 - (T)2 * v2 + v3, B1 = v1 - v3;
     T A2 = v2 - (T)2 * v3 + v4, B2 = (T)3 * v2 - (T)4 * v3 + v4;
-    T r0 = rcp(eps + c1312 * A0 * A0 + (T)0.25 * B0 * B0);
-    T r1 = rcp(eps + c1312 * A1 * A1 + (T)0.25 * B1 * B1);
-    T r2 = rcp(eps + c1312 * A2 * A2 + (T)0.25 * B2 * B2);
+    const T S0 = eps + c1312 * A0 * A0 + (T)0.25 * B0 * B0;
+    const T S1 = eps + c1312 * A1 * A1 + (T)0.25 * B1 * B1;
+    const T S2 = eps + c1312 * A2 * A2 + (T)0.25 * B2 * B2;
+    // 1/S_r from one reciprocal of the product (S_r >= eps, so the product stays normal)
+    const T s12 = S1 * S2, s02 = S0 * S2, s01 = S0 * S1, iP = rcp(S0 * s12);
+    T r0 = s12 * iP, r1 = s02 * iP, r2 = s01 * iP;
     T a0 = (T)0.1 * r0 * r0, a1 = (T)0.6 * r1 * r1, a2 = (T)0.3 * r2 * r2;
     T iS = rcp(a0 + a1 + a2);
     T w0 = a0 * iS, w1 = a1 * iS, w2 = a2 * iS;
@@ -1624,22 +1630,6 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
     T res[8][4];
     weno_adjoint_line(lds, ub, gb, M, t, tpr, active, (T)nl, mx, (T)d.weno_eps, (T)d.dtau, redT, res);
-    if (STAGE == 2) {
-        // lam_n = r + J0^T t2, with r the inverse tau-transform of R~
-        if (active) c2r_pre(Rin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
-        __syncthreads();
-        lds_fft<T, 1>(lds, gb, M, t, active, twst);
-        #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = t + q * tpr;
-            if (active) {
-                quad<T> v = lds_quad(lds, gb, c);
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) res[q][i] += v.v[i];
-            }
-        }
-        __syncthreads();
-    }
     #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
@@ -1647,7 +1637,9 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     }
     __syncthreads();
     lds_fft<T, -1>(lds, gb, M, t, active, twst);
-    if (active) r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw);
+    // stage 2: lam_n = F_tau(J0^T t2) + R~ (the spectrum R~ is added after the
+    // forward transform instead of transforming it back and forth)
+    if (active) r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw, STAGE == 2 ? Rin + so : nullptr);
 }
 
 // Adjoint y-pass.  STAGE 1: L~ -> Lh = F_y L~ (kept, tile-contiguous) and
