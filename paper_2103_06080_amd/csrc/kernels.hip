@@ -1011,9 +1011,12 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // the uniform q NT (buffer accesses with a per-thread base) and its padded
 // LDS slot by the uniform q (dq + dq/16); no slot is out of range, and the
 // first column of the first tile is one per-thread predicate.  Columns start
-// at LDS slot c (P + 32) + (c R mod 32) (P = padded n_y, R = 64/W rows of a
-// column per wave), so that the W row runs of one wave access cover the LDS
-// banks evenly instead of starting on the same bank.
+// at LDS slot c (P + 32) + (c R mod 32) (P = padded n_y, a multiple of 32
+// slots apart, so every column would start on bank 0; R = 32/W rows of a
+// column per half-wave): the LDS serves a 64-bit access of 32 lanes per
+// cycle from 64 four-byte banks, and in the tile copies and the combine the
+// W row runs of one half-wave (R rows of 8 bytes each) then cover the banks
+// once instead of W/2 times (2-way conflicts at W = 4 with R = 64/W).
 //
 // S: precision of the spectral state U and the stage value P (T, or double
 // in FP32 plans that keep their state in FP64: the combine then runs in FP64
@@ -1072,7 +1075,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     const int c = tid & (W - 1), j0 = tid >> lw;
     const int dq = Ny >> 4, sq = dq + (dq >> 4);
     const int Pn = Ny + (Ny >> 4);
-    auto colbase = [&](int col) { return col * (Pn + 32) + ((col << (6 - lw)) & 31); };
+    // (full tiles have W <= 32; the general path does not use these slots)
+    auto colbase = [&](int col) { return col * (Pn + 32) + (lw <= 5 ? ((col << (5 - lw)) & 31) : 0); };
     const int s0 = colbase(c) + padi(j0);               // slot of row j0 (q = 0)
     const int s1 = colbase(c) + padi(Ny - j0);          // slot of row Ny - j0 (q = 0)
     const bool keep_c = !(col0 && c == 0);
