@@ -327,3 +327,20 @@ def test_largest_grid_march_of_y_independent_field_matches_oracle_line(torch_cud
     err = max(rel_l2(got[j], ref) for j in (0, 5000, 8191))
     print("8192 x 8192 y-independent 20-step march %s: rel l2 %.2e" % (dtype, err))
     assert err < bar, err
+
+
+def test_autotune_of_a_7_2k_plan_keeps_its_single_tau_layout(torch_cuda, orc):
+    """The autotuner tries only the tau-pass block and radix schedule a
+    7 2^k plan has (256 threads, radix-16 stages after the radix-7 one) and
+    still picks among the y-pass layouts; the tuned march matches the oracle."""
+    from paper_2103_06080_amd import kzk
+    p = small(448, 128, n_steps=4, A=1e-4)
+    plan = kzk.Plan(p, dtype="f32")
+    u = plan.pack([p.u0])
+    best = plan.autotune(u, 2)
+    tun = plan.tuning()
+    assert tun["tau_threads"] == 256 and tun["tau_fft_radix"] == 16 and tun["y_threads"] == best
+    plan.step(u, 0, p.n_steps)
+    assert plan.poll() == 0
+    assert rel_l2(plan.unpack(u)[0], orc.run(p)) < TOL["f32"]
+    plan.close()
