@@ -100,6 +100,11 @@ MUTATIONS = [
      [TR.test_velocity_equals_cartesian_mode_sum]),
     ("velocity: amplitude without 1/N", "amp[n] = sqrt(E / (double)N) / c->vel_c0;",
      "amp[n] = sqrt(E) / c->vel_c0;", None, [TR.test_velocity_field_is_bounded_as_stated]),
+    ("velocity: energy halved", "amp[n] = sqrt(E / (double)N) / c->vel_c0;",
+     "amp[n] = sqrt(E / (double)(2 * N)) / c->vel_c0;", None,
+     [TR.test_velocity_field_carries_the_energy_of_its_spectrum]),
+    ("velocity: spectrum without its 1/8", "double E = 0.125 * sq(c->vel_sigma_u)", "double E = sq(c->vel_sigma_u)",
+     None, [TR.test_velocity_field_carries_the_energy_of_its_spectrum]),
     ("velocity: mode vector not normal to K", "double U1 = -amp[n] * sin(th), U2 = amp[n] * cos(th);",
      "double U1 = amp[n] * cos(th), U2 = amp[n] * sin(th);", None, [TR.test_velocity_field_is_divergence_free]),
     ("mixed-radix FFT: odd-length sum with the wrong sign",

@@ -6,7 +6,8 @@ it is -d_tau(nl u^2/2 - 2 pi U_par u) - d_y(U_perp u) + (d_y U_perp) u, with a
 WENO5/LF flux difference along each direction.  The random velocity field is
 the one of Sec. 2 (Algorithm 1).  Checked against: finite differences and
 the divergence-free construction of the field, the paper's bound on its
-size, a Cartesian evaluation of the mode sum, the Burgers b where the field
+size, the energy its spectrum integrates to (closed form), a Cartesian
+evaluation of the mode sum, the Burgers b where the field
 vanishes, fifth-order convergence of b to its exact value on smooth data,
 exact telescoping of the flux differences, exact translation by a constant
 U_par, and second-order convergence of the march.
@@ -220,3 +221,23 @@ def test_transverse_transport_term_equals_exact_evaluation(orc):
         ref = _exact_lf_line(f, a, dy, p.weno_eps)
         ref = np.array([float(ref[j] + Fr(float(duperp[j])) * U[j]) for j in range(ny)])
         assert np.abs(b[:, k] - ref).max() <= 1e-13 * np.abs(ref).max(), k
+
+
+def test_velocity_field_carries_the_energy_of_its_spectrum(orc):
+    """The spectrum E(K) = sigma_u^2 K^3 L^4 exp(-(K L / 2)^2) / 8 integrates to
+    sigma_u^2 over K >= 0 (closed form: int K^3 e^{-a K^2} dK = 1/(2 a^2),
+    a = L^2/4).  With N modes equispaced in [0.1/L, 9/L] (spacing dK) and
+    |U~_n|^2 = E(K_n) / N / c0^2, the field's mean square over the plane is
+    sum_n |U~_n|^2 / 2 = (sum_n E(K_n) dK) / (2 N dK c0^2), i.e. sigma_u^2 /
+    (2 N dK c0^2) up to the Riemann sum; checked on a spatial average over a
+    large window (sampling error a few per cent), which catches a wrong
+    amplitude normalisation (a missing square root, 1/N or 1/2)."""
+    p = medium_problem(n_modes=200, seed=11)
+    L = 4 * p.vel_lambda
+    dK = (9.0 / L - 0.1 / L) / (p.vel_modes - 1)
+    want = p.vel_sigma_u ** 2 / (2 * p.vel_modes * dK * p.vel_c0 ** 2)
+    u = I.splitmix_uniform_array(21, 2 * 4000).reshape(4000, 2)
+    xs, ys = 5000.0 * u[:, 0], 5000.0 * u[:, 1]
+    v = np.array([orc.velocity(p, x, y)[:2] for x, y in zip(xs, ys)])
+    got = float((v ** 2).sum(axis=1).mean())
+    assert abs(got / want - 1) < 0.1, (got, want)
