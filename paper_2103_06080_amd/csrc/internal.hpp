@@ -120,10 +120,11 @@ template <typename T>
 hipError_t launch_dc(int stage, const InstDesc* d_desc, int n_inst, void* C, void* P, void* U, const void* By,
                      const void* twst, int step, hipStream_t s);
 
+// gk as for launch_tau (M = 7 * 2^gk lines, tw of length n_tau).
 template <typename T>
 hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
                           const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
-                          int log2_ntw, int node, unsigned* status, hipStream_t s);
+                          int log2_ntw, int node, int gk, unsigned* status, hipStream_t s);
 
 template <typename T>
 hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,

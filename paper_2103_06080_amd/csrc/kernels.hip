@@ -446,7 +446,7 @@ __device__ __forceinline__ void c2r_pre_gen(const cpx<T>* __restrict__ X, SpecId
 
 template <typename T, int M>
 __device__ __forceinline__ void r2c_post_gen(const cpx<T>* lds, int base, cpx<T>* __restrict__ X, SpecIdx ix, int t,
-                                             const cpx<T>* __restrict__ tw) {
+                                             const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ add = nullptr) {
     constexpr int tpr = M / 16;
     #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -457,11 +457,12 @@ __device__ __forceinline__ void r2c_post_gen(const cpx<T>* lds, int base, cpx<T>
         cpx<T> a, b;
         r2c_pair(zk, zm, tw[k], a, b);
         if (k == 0) {
-            X[0] = cpx<T>{a.x, b.x};
+            a = cpx<T>{a.x, b.x};
+            X[0] = add ? a + add[0] : a;
             continue;
         }
-        X[ix(k)] = a;
-        if (2 * k != M) X[ix(M - k)] = b;
+        X[ix(k)] = add ? a + add[ix(k)] : a;
+        if (2 * k != M) X[ix(M - k)] = add ? b + add[ix(M - k)] : b;
     }
 }
 
@@ -1474,10 +1475,13 @@ __device__ __forceinline__ void weno_face_grad(T v0, T v1, T v2, T v3, T v4, T e
 // ubuf: the line u (logical base ub); gbuf: the cotangent of b (base gb).
 // Returns the result for the thread's own points 4c..4c+3 of its chunks
 // c = t + q*tpr in out[q][.].  Both buffers are overwritten (halo exchange).
-template <typename T>
-__device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, int M, int t, int tpr, bool active,
-                                                  T nlT, T mx, T eps, T dtau, T* redT, T out[8][4]) {
+// GK > 0: M = 7 * 2^GK (chunk indices wrap by a select); tpg: threads of a
+// line's group for the line sums (tpr for power-of-two M).
+template <typename T, int GK = 0>
+__device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, int M, int t, int tpr, int tpg,
+                                                  bool active, T nlT, T mx, T eps, T dtau, T* redT, T out[8][4]) {
     const int Nc = M >> 1;
+    auto wrapc = [&](int c) { return GK > 0 ? (c < 0 ? c + Nc : (c >= Nc ? c - Nc : c)) : (c & (Nc - 1)); };
     const T alpha = (T)fabs(nlT) * mx;
     const T idt = (T)1 / dtau;
     T halo[8][5];
@@ -1491,11 +1495,11 @@ __device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, i
         #pragma unroll
         for (int i = 0; i < 5; ++i) halo[q][i] = 0;
         if (active) {
-            quad<T> a = lds_quad(lds, ub, (c - 1) & (Nc - 1)), b = lds_quad(lds, ub, c),
-                    e = lds_quad(lds, ub, (c + 1) & (Nc - 1));
+            quad<T> a = lds_quad(lds, ub, wrapc(c - 1)), b = lds_quad(lds, ub, c),
+                    e = lds_quad(lds, ub, wrapc(c + 1));
             T u[12] = {a.v[0], a.v[1], a.v[2], a.v[3], b.v[0], b.v[1], b.v[2], b.v[3],
                        e.v[0], e.v[1], e.v[2], e.v[3]};
-            quad<T> g0 = lds_quad(lds, gb, c), g1 = lds_quad(lds, gb, (c + 1) & (Nc - 1));
+            quad<T> g0 = lds_quad(lds, gb, c), g1 = lds_quad(lds, gb, wrapc(c + 1));
             T gg[5] = {g0.v[0], g0.v[1], g0.v[2], g0.v[3], g1.v[0]};
             T fp[12], fm[12], accP[12], accM[12];
             #pragma unroll
@@ -1544,8 +1548,8 @@ __device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, i
             halo[q][4] = contrib[10];
         }
     }
-    abar = line_sum(abar, tpr, redT);
-    nties = line_sum(nties, tpr, redT);
+    abar = line_sum(abar, tpg, redT);
+    nties = line_sum(nties, tpg, redT);
     __syncthreads();
     // halo exchange: left halo (points 4c-2, 4c-1) into the u buffer slots
     // of chunk c; right halo (points 4c+4..4c+6) into the g buffer.
@@ -1565,8 +1569,8 @@ __device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, i
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
         if (active) {
-            quad<T> lh = lds_quad(lds, ub, (c + 1) & (Nc - 1));   // chunk c+1's left halo: points 4c+2, 4c+3
-            quad<T> rh = lds_quad(lds, gb, (c - 1) & (Nc - 1));   // chunk c-1's right halo: points 4c..4c+2
+            quad<T> lh = lds_quad(lds, ub, wrapc(c + 1));   // chunk c+1's left halo: points 4c+2, 4c+3
+            quad<T> rh = lds_quad(lds, gb, wrapc(c - 1));   // chunk c-1's right halo: points 4c..4c+2
             out[q][0] += rh.v[0];
             out[q][1] += rh.v[1];
             out[q][2] += rh.v[2] + lh.v[0];
@@ -1582,7 +1586,9 @@ __device__ __forceinline__ void weno_adjoint_line(cpx<T>* lds, int ub, int gb, i
 // Adjoint tau-pass.  STAGE 1: cotangent T~1 (mixed spectrum) and u* ->
 // mu = J1^T t1 -> M~.  STAGE 2: T~2, R~ and u^n -> lam_n = r + J0^T t2 -> L~.
 // (The factor h is carried by the pre-scaled tables of the adjoint y-pass.)
-template <typename T, int STAGE>
+// GK > 0: every instance has M = 7 * 2^GK (lines in groups of 2^(GK-1)
+// threads, as in the forward tau-kernel; tw is the table e^{-2 pi i k/n_tau}).
+template <typename T, int STAGE, int GK = 0>
 __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __restrict__ descs,
                                                               const TauItem* __restrict__ items,
                                                               const cpx<T>* __restrict__ Tin,
@@ -1597,17 +1603,23 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
     __shared__ int redI[TAU_THREADS / 64];
     const TauItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const InstDesc& d = descs[it.inst];
-    const int M = d.M, N = 2 * M;
+    constexpr int MG = GK > 0 ? (7 << GK) : 16;    // compile-time M of the 7 * 2^K lines
+    const int M = GK > 0 ? MG : d.M, N = 2 * M;
     const int tpr = M >> 4;
-    const int r = threadIdx.x / tpr, t = threadIdx.x & (tpr - 1);
+    const int tpg = GK > 0 ? (1 << (GK - 1)) : tpr;
+    const int r = threadIdx.x / tpg, t = threadIdx.x & (tpg - 1);
     const int row = it.row0 + r;
-    const bool active = (r < (TAU_THREADS * 16) / M) && (row < d.n_y);
+    const int rows = GK > 0 ? (TAU_THREADS >> (GK - 1)) : (TAU_THREADS * 16) / M;
+    const bool active = (GK == 0 || t < tpr) && (r < rows) && (row < d.n_y);
     const int gb = r * M;                          // cotangent line
     const int ub = TAU_THREADS * 16 + r * M;        // u line (second half of the buffer)
     const SpecIdx ix = spec_idx(d.log2W, d.n_y, true);
     const long long so = d.off_state + ((long long)row << d.log2W);
 
-    if (active) c2r_pre(Tin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    if (active) {
+        if constexpr (GK > 0) c2r_pre_gen<T, MG>(Tin + so, ix, lds, gb, t, tw, (T)1 / (T)N);
+        else c2r_pre(Tin + so, ix, lds, gb, M, t, tpr, tw, log2_ntw, (T)1 / (T)N);
+    }
     // the stored physical line
     T mx = 0;
     int bad = 0;
@@ -1627,23 +1639,28 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
         }
     }
     __syncthreads();
-    lds_fft<T, 1>(lds, gb, M, t, active, twst);
-    mx = line_max(mx, tpr, redT);
-    bad = line_or(bad, tpr, redI);
+    if constexpr (GK > 0) gen_fft<T, 1, GK>(lds, gb, t, active, tw);
+    else lds_fft<T, 1>(lds, gb, M, t, active, twst);
+    mx = line_max(mx, tpg, redT);
+    bad = line_or(bad, tpg, redI);
     if (active && t == 0 && bad) atomicOr(status, ST_NONFINITE);
     const double nl = d.nl_node ? d.nl_node[node] : d.nl_const;
     T res[8][4];
-    weno_adjoint_line(lds, ub, gb, M, t, tpr, active, (T)nl, mx, (T)d.weno_eps, (T)d.dtau, redT, res);
+    weno_adjoint_line<T, GK>(lds, ub, gb, M, t, tpr, tpg, active, (T)nl, mx, (T)d.weno_eps, (T)d.dtau, redT, res);
     #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int c = t + q * tpr;
         if (active) lds_quad_st(lds, gb, c, quad<T>{{res[q][0], res[q][1], res[q][2], res[q][3]}});
     }
     __syncthreads();
-    lds_fft<T, -1>(lds, gb, M, t, active, twst);
+    if constexpr (GK > 0) gen_fft<T, -1, GK>(lds, gb, t, active, tw);
+    else lds_fft<T, -1>(lds, gb, M, t, active, twst);
     // stage 2: lam_n = F_tau(J0^T t2) + R~ (the spectrum R~ is added after the
     // forward transform instead of transforming it back and forth)
-    if (active) r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw, STAGE == 2 ? Rin + so : nullptr);
+    if (active) {
+        if constexpr (GK > 0) r2c_post_gen<T, MG>(lds, gb, out + so, ix, t, tw, STAGE == 2 ? Rin + so : nullptr);
+        else r2c_post(lds, gb, out + so, ix, M, t, tpr, tw, log2_ntw, STAGE == 2 ? Rin + so : nullptr);
+    }
 }
 
 // Adjoint y-pass.  STAGE 1: L~ -> Lh = F_y L~ (kept, tile-contiguous) and
@@ -2049,11 +2066,10 @@ hipError_t launch_tables(const InstDesc* d_desc, int inst, int per_tile, int n_t
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
-                          const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
-                          int log2_ntw, int node, unsigned* status, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
+template <typename T, int GK>
+static hipError_t launch_tau_adj_gk(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items,
+                                    const void* Tin, const void* Rin, const T* ustore, void* out, const void* tw,
+                                    const void* twst, int log2_ntw, int node, unsigned* status, hipStream_t s) {
     dim3 g(n_items), b(TAU_THREADS);
     const cpx<T>* ti = static_cast<const cpx<T>*>(Tin);
     const cpx<T>* ri = static_cast<const cpx<T>*>(Rin);
@@ -2061,10 +2077,27 @@ hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_it
     const cpx<T>* w = static_cast<const cpx<T>*>(tw);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((tau_adj_kernel<T, 1>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
+        hipLaunchKernelGGL((tau_adj_kernel<T, 1, GK>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
     else
-        hipLaunchKernelGGL((tau_adj_kernel<T, 2>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
+        hipLaunchKernelGGL((tau_adj_kernel<T, 2, GK>), g, b, 0, s, d_desc, d_items, ti, ri, ustore, o, w, ws, log2_ntw, node, status);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_items, int n_items, const void* Tin,
+                          const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
+                          int log2_ntw, int node, int gk, unsigned* status, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (gk) {
+    case 0: return launch_tau_adj_gk<T, 0>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 4: return launch_tau_adj_gk<T, 4>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 5: return launch_tau_adj_gk<T, 5>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 6: return launch_tau_adj_gk<T, 6>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 7: return launch_tau_adj_gk<T, 7>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 8: return launch_tau_adj_gk<T, 8>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    case 9: return launch_tau_adj_gk<T, 9>(stage, d_desc, d_items, n_items, Tin, Rin, ustore, out, tw, twst, log2_ntw, node, status, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int NT>
@@ -2134,7 +2167,7 @@ void stage_twiddles(double* out) {
     template hipError_t launch_yweno<T>(const InstDesc*, const YwItem*, int, const T*, T*, int, unsigned*,           \
                                         hipStream_t);                                                                \
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
-                                          const T*, void*, const void*, const void*, int, int, unsigned*,            \
+                                          const T*, void*, const void*, const void*, int, int, int, unsigned*,       \
                                           hipStream_t);                                                              \
     template hipError_t launch_y_adj<T>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,    \
                                         void*, const void*, const void*, hipStream_t);

@@ -4,8 +4,9 @@ groups of 2^(k-1), index wraps mod n_tau) against numpy's real FFT and the
 FP64 oracle's mixed-radix transform, on every supported length 224 .. 7168,
 with several lines per block and ragged last blocks, general and full-tile
 y-passes, column tiles capped at the power of two dividing M, batched plans,
-transport, and the full-size grid of set 3 against the closed form of the
-linear march and the oracle's march of a y-independent field.
+transport, the adjoint, and the full-size grids of sets 3 and 4 against the
+closed form of the linear march and the oracle's march of a y-independent
+field.
 
 Bars: FP64 <= 1e-12 relative l2 (marches; 1e-14-level for transforms), FP32
 <= 1e-4 for marches.
@@ -163,16 +164,35 @@ def test_transport_on_7_2k_grid_matches_oracle(torch_cuda, orc, dtype, scheme, r
     assert err < TOL[dtype], err
 
 
-def test_7_2k_plan_rejects_the_adjoint_and_wide_tau_blocks(torch_cuda):
+def test_7_2k_plan_rejects_wide_tau_blocks(torch_cuda):
     from paper_2103_06080_amd import kzk
     p = small(448, 64, n_steps=2)
     plan = kzk.Plan(p, dtype="f32")
     assert plan.tau_threads == 256
     with pytest.raises(kzk.KZKError):
         plan.set_tau_threads(512)
-    u = plan.pack([p.u0])
     with pytest.raises(kzk.KZKError):
-        plan.adjoint(u, u.clone(), 0, 2, ckpt=1)
+        plan.set_tau_fft_radix(8)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt,ny,n_steps,ckpt,scheduled", [(448, 32, 5, 2, True), (224, 64, 6, 3, False),
+                                                         (1792, 16, 3, 3, True)])
+def test_adjoint_on_7_2k_grid_matches_oracle(torch_cuda, orc, dtype, nt, ny, n_steps, ckpt, scheduled):
+    """The discrete adjoint with the mixed-radix tau-transforms (the adjoint
+    tau-pass in its 7 2^k form) against the oracle's adjoint."""
+    from paper_2103_06080_amd import kzk
+    from test_gpu_adjoint import nwave_problem
+    p = nwave_problem(nt, ny, n_steps, scheduled=scheduled)
+    lam = I.random_field(77, (ny, nt))
+    ref = orc.adjoint(p, lam, ckpt=ckpt)
+    plan = kzk.Plan(p, dtype=dtype)
+    g = plan.adjoint(plan.pack([p.u0]), plan.pack([lam]), 0, n_steps, ckpt)
+    assert plan.poll() == 0
+    err = rel_l2(plan.unpack(g)[0], ref)
+    print("7 2^k adjoint %s %dx%d %d steps: rel l2 %.3e" % (dtype, nt, ny, n_steps, err))
+    assert err < (1e-12 if dtype == "f64" else 1e-4)
     plan.close()
 
 

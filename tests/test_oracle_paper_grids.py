@@ -75,3 +75,20 @@ def test_mixed_radix_fft_other_odd_factors_match_numpy(orc, m, a):
     assert np.abs(orc.fft(x) - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
     back = orc.fft(orc.fft(x), 1) / n
     assert np.abs(back - x).max() < 1e-13 * np.abs(x).max()
+
+
+def test_adjoint_on_a_7_2k_grid_matches_central_differences(orc):
+    """The oracle's discrete adjoint with mixed-radix transforms: <grad, d>
+    against a central difference of L(u0) = <u(x_end), lam> along d."""
+    import dataclasses
+    from test_gpu_adjoint import nwave_problem
+    p = nwave_problem(448, 32, 5, scheduled=True)
+    lam = I.random_field(77, (32, 448))
+    g = orc.adjoint(p, lam, ckpt=2)
+    d = I.random_field(5, (32, 448))
+    e = 1e-6
+
+    def L(u):
+        return float((orc.run(dataclasses.replace(p, u0=u)) * lam).sum())
+    fd = (L(p.u0 + e * d) - L(p.u0 - e * d)) / (2 * e)
+    assert abs(fd - float((g * d).sum())) < 1e-4 * abs(fd)
