@@ -62,7 +62,7 @@ typedef struct {
                                then every solve of the plan has the same n_tau).  With
                                n_y = 8192 the plan needs y-pass blocks of 512 or more
                                threads and full column tiles in every solve
-                               (KZK_ERR_SIZE otherwise); no adjoint there         */
+                               (KZK_ERR_SIZE otherwise)                            */
     double tau0, L_tau;     /* periodic tau box [tau0, tau0 + L_tau)                      */
     double y0, L_y;         /* periodic y box [y0, y0 + L_y)                              */
     double x0, h;           /* marching origin and step: x_n = x0 + n h (paper: Delta sigma) */
@@ -143,8 +143,8 @@ kzk_status kzk_step(kzk_plan *plan, void *u_dev, int32_t first_step, int32_t n_s
  * whose stored fields and checkpoints fit in half of the device memory free
  * at the call.  Asynchronous; the result does not depend on the interval.  For ExpRK22
  * with the mean mode zeroed and the Burgers b (scheme 0, reg_eps 0, vel 0,
- * state_fp64 0 in FP32) and n_y <= 4096 (n_tau a power of two or 7 * 2^k);
- * KZK_ERR_ARG otherwise. */
+ * state_fp64 0 in FP32), on every grid kzk_step takes; KZK_ERR_ARG
+ * otherwise. */
 kzk_status kzk_adjoint(kzk_plan *plan, const void *u0_dev, const void *lam_dev, int32_t first_step,
                        int32_t n_steps, int32_t ckpt_every, void *grad_dev);
 

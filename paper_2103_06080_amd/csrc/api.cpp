@@ -438,10 +438,10 @@ hipError_t tau_adj(kzk_plan* p, int stage, const void* Tin, const void* Rin, con
 hipError_t y_adj(kzk_plan* p, int stage, const void* In, void* Lh, void* Tout, void* Rout) {
     ProfScope ps(p, KZK_KIND_ADJ_Y);
     if (p->dtype == KZK_F32)
-        return kzk::launch_y_adj<float>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout,
-                                        p->dTab, p->dTwSt, p->stream);
-    return kzk::launch_y_adj<double>(stage, p->y_threads, p->dDesc, p->dY, p->n_y_items, In, Lh, Tout, Rout, p->dTab,
-                                     p->dTwSt, p->stream);
+        return kzk::launch_y_adj<float>(stage, p->y_threads, p->max_ny > 4096, p->dDesc, p->dY, p->n_y_items, In,
+                                        Lh, Tout, Rout, p->dTab, p->dTwSt, p->stream);
+    return kzk::launch_y_adj<double>(stage, p->y_threads, p->max_ny > 4096, p->dDesc, p->dY, p->n_y_items, In, Lh,
+                                     Tout, Rout, p->dTab, p->dTwSt, p->stream);
 }
 
 // u -> state: tau-spectrum per row (dC), then the full spectrum (dU).
@@ -1066,7 +1066,7 @@ extern "C" kzk_status kzk_adjoint(kzk_plan* p, const void* u0, const void* lam, 
                                   int32_t ckpt, void* grad) {
     if (!p || !u0 || !lam || !grad || ckpt < 0) return KZK_ERR_ARG;
     // ExpRK22, zeroed mean, Burgers b, state in the working precision
-    if (p->scheme != 0 || p->any_reg || p->transport || p->s64 || p->max_ny > 4096) return KZK_ERR_ARG;
+    if (p->scheme != 0 || p->any_reg || p->transport || p->s64) return KZK_ERR_ARG;
     kzk_status st = check_range(p, first, n);
     if (st != KZK_OK) return st;
     const size_t cz = 2 * p->esz, sb = p->state_elems * cz, ub = p->u_off[p->n_inst] * p->esz;

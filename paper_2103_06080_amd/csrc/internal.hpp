@@ -126,9 +126,11 @@ hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_it
                           const void* Rin, const T* ustore, void* out, const void* tw, const void* twst,
                           int log2_ntw, int node, int gk, unsigned* status, hipStream_t s);
 
+// big: some instance has n_y = 8192 (nt 512, or 1024 in FP32).
 template <typename T>
-hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
-                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s);
+hipError_t launch_y_adj(int stage, int nt, bool big, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                        const void* In, void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst,
+                        hipStream_t s);
 
 // Number of complex entries of the per-stage twiddle table (all lengths).
 int stage_twiddle_entries();

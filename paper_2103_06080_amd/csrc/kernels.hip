@@ -1667,8 +1667,10 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
 // T~1 = F_y^-1 conj(h Phi2) Z Lh.  STAGE 2: M~ and Lh ->
 // T~2 = F_y^-1 Z [conj(h(Phi1 - Phi2)) Lh + conj(h Phi1) Mh] and
 // R~ = F_y^-1 conj(E) (Lh + Mh).  Column 0 (DC, tau-Nyquist) pointwise in y;
-// its Lh slot holds the raw column.
-template <typename T, int NT, int STAGE>
+// its Lh slot holds the raw column.  BIG: some instance has n_y = 8192,
+// whose per-thread twiddles do not fit in registers beside the held
+// values; stage 1 then loads them per transform stage as stage 2 does.
+template <typename T, int NT, int STAGE, bool BIG = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_adj_kernel(const InstDesc* __restrict__ descs,
                                                    const YItem* __restrict__ items, const cpx<T>* __restrict__ In,
                                                    cpx<T>* __restrict__ Lh, cpx<T>* __restrict__ Tout,
@@ -1699,11 +1701,11 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_a
     // transforms; stage 2 keeps 16 values per thread across its second
     // transform and loads its twiddles per transform stage instead.
     cpx<T> ytw[2][15];
-    if (STAGE == 1) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
+    if constexpr (STAGE == 1 && !BIG) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
     cpx<T> keep[16];
     tile_load<T, NT>(lds, It, ne, tid, W, lw, Ny, keep);
     __syncthreads();
-    if (STAGE == 1)
+    if constexpr (STAGE == 1 && !BIG)
         lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
     else
         lds_fft<T, -1, false>(lds, fc * Ny, Ny, ft, act, twst);
@@ -1728,7 +1730,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_a
         }
     }
     __syncthreads();
-    if (STAGE == 1)
+    if constexpr (STAGE == 1 && !BIG)
         lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
     else
         lds_fft<T, 1, false>(lds, fc * Ny, Ny, ft, act, twst);
@@ -2100,7 +2102,7 @@ hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_it
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool BIG>
 static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
                                   void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s) {
     dim3 g(n_items), b(NT);
@@ -2111,22 +2113,36 @@ static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1, BIG>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     else
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2, BIG>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y_adj(int stage, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
-                        void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s) {
+hipError_t launch_y_adj(int stage, int nt, bool big, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                        const void* In, void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst,
+                        hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (big) {   // n_y = 8192 fills 512 threads per column
+        switch (nt) {
+        case 512:
+            return launch_y_adj_nt<T, 512, true>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
+        case 1024:
+            if constexpr (sizeof(T) == 4)
+                return launch_y_adj_nt<T, 1024, true>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs,
+                                                      twst, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (nt) {
-    case 256: return launch_y_adj_nt<T, 256>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
-    case 512: return launch_y_adj_nt<T, 512>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
+    case 256: return launch_y_adj_nt<T, 256, false>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
+    case 512: return launch_y_adj_nt<T, 512, false>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_adj_nt<T, 1024>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst, s);
+            return launch_y_adj_nt<T, 1024, false>(stage, d_desc, d_items, n_items, In, Lh, Tout, Rout, tabs, twst,
+                                                   s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -2169,8 +2185,8 @@ void stage_twiddles(double* out) {
     template hipError_t launch_tau_adj<T>(int, const InstDesc*, const TauItem*, int, const void*, const void*,      \
                                           const T*, void*, const void*, const void*, int, int, int, unsigned*,       \
                                           hipStream_t);                                                              \
-    template hipError_t launch_y_adj<T>(int, int, const InstDesc*, const YItem*, int, const void*, void*, void*,    \
-                                        void*, const void*, const void*, hipStream_t);
+    template hipError_t launch_y_adj<T>(int, int, bool, const InstDesc*, const YItem*, int, const void*, void*,     \
+                                        void*, void*, const void*, const void*, hipStream_t);
 KZK_INSTANTIATE(float)
 KZK_INSTANTIATE(double)
 #undef KZK_INSTANTIATE

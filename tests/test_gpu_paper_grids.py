@@ -4,7 +4,7 @@ groups of 2^(k-1), index wraps mod n_tau) against numpy's real FFT and the
 FP64 oracle's mixed-radix transform, on every supported length 224 .. 7168,
 with several lines per block and ragged last blocks, general and full-tile
 y-passes, column tiles capped at the power of two dividing M, batched plans,
-transport, the adjoint, and the full-size grids of sets 3 and 4 against the
+transport, the adjoint (also with 8192-row columns), and the full-size grids of sets 3 and 4 against the
 closed form of the linear march and the oracle's march of a y-independent
 field.
 
@@ -278,6 +278,27 @@ def test_transport_with_8192_rows_matches_oracle(torch_cuda, orc, dtype):
     assert err < TOL[dtype], err
 
 
+@pytest.mark.parametrize("dtype,yt,nt,n_steps", [("f64", 512, 32, 3), ("f32", 1024, 32, 3), ("f32", 512, 32, 3),
+                                                  ("f64", 512, 448, 2)])
+def test_adjoint_with_8192_rows_matches_oracle(torch_cuda, orc, dtype, yt, nt, n_steps):
+    """The discrete adjoint with 8192-point column transforms (twiddles
+    loaded per transform stage in both adjoint y-passes), in full tiles of
+    1 or 2 columns, against the oracle's adjoint; on 448 x 8192 with the
+    mixed-radix adjoint tau-pass as well."""
+    from paper_2103_06080_amd import kzk
+    from test_gpu_adjoint import nwave_problem
+    p = nwave_problem(nt, 8192, n_steps, scheduled=True)
+    lam = I.random_field(77, (8192, nt))
+    ref = orc.adjoint(p, lam, ckpt=1)
+    plan = kzk.Plan(p, dtype=dtype, y_threads=yt)
+    g = plan.adjoint(plan.pack([p.u0]), plan.pack([lam]), 0, n_steps, 2)
+    assert plan.poll() == 0
+    err = rel_l2(plan.unpack(g)[0], ref)
+    print("8192-row adjoint %s %d x 8192 (%d threads): rel l2 %.3e" % (dtype, nt, yt, err))
+    assert err < (1e-12 if dtype == "f64" else 1e-4)
+    plan.close()
+
+
 def test_8192_rows_need_full_tiles_of_512_threads(torch_cuda):
     from paper_2103_06080_amd import kzk
     p = small(32, 8192, n_steps=2)
@@ -287,9 +308,6 @@ def test_8192_rows_need_full_tiles_of_512_threads(torch_cuda):
         plan.set_y_threads(256)
     plan.set_y_threads(512)
     assert plan.y_threads == 512
-    u = plan.pack([p.u0])
-    with pytest.raises(kzk.KZKError):
-        plan.adjoint(u, u.clone(), 0, 2, ckpt=1)
     plan.close()
     # a solve with few rows next to the 8192-row one leaves no full-tile layout
     with pytest.raises(kzk.KZKError):
