@@ -1024,11 +1024,14 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // with the step's multipliers evaluated in FP64, and only the inputs of the
 // inverse y-transform are rounded to T).
 //
-// BIG (full tiles only): some instance has n_y = 8192, whose column
-// transform has three stages with twiddles, more than the registers hold
-// beside the tile: this variant loads the twiddles of every column transform
-// per stage (look-ahead) instead of holding them.
-template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool BIG = false>
+// LTW: the twiddles of every column transform are loaded per transform
+// stage (with look-ahead) instead of held in registers across tiles.  Taken
+// by full tiles when some instance has n_y = 8192 (whose transform has three
+// stages with twiddles, more than the registers hold beside the tile), and
+// by the FP32 general-tile blocks, whose element indexing leaves no room for
+// held twiddles under the 128-VGPR cap (they would spill about 120 VGPRs to
+// scratch; the loaded form needs none and gives bit-identical results).
+template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool LTW = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
         const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<S>* __restrict__ P, cpx<S>* __restrict__ U,
@@ -1112,7 +1115,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         }
     }
     if (Ny != tw_ny) {
-        if constexpr (!BIG) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
+        if constexpr (!LTW) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
         tw_ny = Ny;
     }
     if constexpr (FULL) {
@@ -1123,7 +1126,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     }
     __syncthreads();
     if (STAGE == 0) {
-        if constexpr (BIG) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
+        if constexpr (LTW) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
         else lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
         if constexpr (FULL) {
             const auto rc = buf_rsrc(Ct), ru = buf_rsrc(Ut);
@@ -1142,7 +1145,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         continue;
     }
 
-    if constexpr (BIG) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
+    if constexpr (LTW) lds_fft<T, -1>(fbuf, fbase, Ny, ft, act, twst);
     else lds_fft_held<T, -1>(fbuf, fbase, Ny, ft, act, ytw);
     // combine: the symbol is even in ky, so one table row n serves y-wavenumber
     // indices n and Ny - n.  A thread has at most 9 half-tile items
@@ -1359,7 +1362,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     }
     }
     __syncthreads();
-    if constexpr (BIG) lds_fft<T, 1>(fbuf, fbase, Ny, ft, act, twst);
+    if constexpr (LTW) lds_fft<T, 1>(fbuf, fbase, Ny, ft, act, twst);
     else lds_fft_held<T, 1>(fbuf, fbase, Ny, ft, act, ytw);
     if constexpr (FULL) {
         const auto rc = buf_rsrc(Ct);
@@ -1667,10 +1670,10 @@ __global__ __launch_bounds__(TAU_THREADS) void tau_adj_kernel(const InstDesc* __
 // T~1 = F_y^-1 conj(h Phi2) Z Lh.  STAGE 2: M~ and Lh ->
 // T~2 = F_y^-1 Z [conj(h(Phi1 - Phi2)) Lh + conj(h Phi1) Mh] and
 // R~ = F_y^-1 conj(E) (Lh + Mh).  Column 0 (DC, tau-Nyquist) pointwise in y;
-// its Lh slot holds the raw column.  BIG: some instance has n_y = 8192,
+// its Lh slot holds the raw column.  LTW: some instance has n_y = 8192,
 // whose per-thread twiddles do not fit in registers beside the held
 // values; stage 1 then loads them per transform stage as stage 2 does.
-template <typename T, int NT, int STAGE, bool BIG = false>
+template <typename T, int NT, int STAGE, bool LTW = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_adj_kernel(const InstDesc* __restrict__ descs,
                                                    const YItem* __restrict__ items, const cpx<T>* __restrict__ In,
                                                    cpx<T>* __restrict__ Lh, cpx<T>* __restrict__ Tout,
@@ -1701,11 +1704,11 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_a
     // transforms; stage 2 keeps 16 values per thread across its second
     // transform and loads its twiddles per transform stage instead.
     cpx<T> ytw[2][15];
-    if constexpr (STAGE == 1 && !BIG) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
+    if constexpr (STAGE == 1 && !LTW) lds_fft_twiddles<T>(Ny, ft, twst, ytw);
     cpx<T> keep[16];
     tile_load<T, NT>(lds, It, ne, tid, W, lw, Ny, keep);
     __syncthreads();
-    if constexpr (STAGE == 1 && !BIG)
+    if constexpr (STAGE == 1 && !LTW)
         lds_fft_held<T, -1>(lds, fc * Ny, Ny, ft, act, ytw);
     else
         lds_fft<T, -1, false>(lds, fc * Ny, Ny, ft, act, twst);
@@ -1730,7 +1733,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_a
         }
     }
     __syncthreads();
-    if constexpr (STAGE == 1 && !BIG)
+    if constexpr (STAGE == 1 && !LTW)
         lds_fft_held<T, 1>(lds, fc * Ny, Ny, ft, act, ytw);
     else
         lds_fft<T, 1, false>(lds, fc * Ny, Ny, ft, act, twst);
@@ -1877,7 +1880,7 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NT, bool FULL, typename S, bool BIG>
+template <typename T, int NT, bool FULL, typename S, bool LTW>
 static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
                                void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
                                int step, hipStream_t s) {
@@ -1890,28 +1893,28 @@ static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S, BIG>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     return hipGetLastError();
 }
 
 // s64: FP32 plan with the state in FP64
-template <typename T, int NT, bool FULL, bool BIG>
+template <typename T, int NT, bool FULL, bool LTW>
 static hipError_t launch_y_nt(int stage, int s64, const InstDesc* d_desc, const YItem* d_items, int n_items,
                               int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                               const void* twst, int step, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         if (s64)
-            return launch_y_nts<T, NT, FULL, double, BIG>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+            return launch_y_nts<T, NT, FULL, double, LTW>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P,
                                                           U, tabs, twst, step, s);
     }
-    return launch_y_nts<T, NT, FULL, T, BIG>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
+    return launch_y_nts<T, NT, FULL, T, LTW>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
                                              step, s);
 }
 
@@ -1922,10 +1925,13 @@ static int y_resident_nt(int device, int full) {
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0)
         return 0;
     int lo = 1 << 30;
-    // the 8192-row variant exists for blocks of 512 and 1024 threads only
+    // the 8192-row variant exists for blocks of 512 and 1024 threads only;
+    // FP32 general tiles load their twiddles per stage
     constexpr bool big = NT >= 512;
-    const void* fns[3][3] = {{(const void*)y_kernel<T, NT, 0, false, S>, (const void*)y_kernel<T, NT, 1, false, S>,
-                              (const void*)y_kernel<T, NT, 2, false, S>},
+    constexpr bool gl = sizeof(T) == 4;
+    const void* fns[3][3] = {{(const void*)y_kernel<T, NT, 0, false, S, gl>,
+                              (const void*)y_kernel<T, NT, 1, false, S, gl>,
+                              (const void*)y_kernel<T, NT, 2, false, S, gl>},
                              {(const void*)y_kernel<T, NT, 0, true, S>, (const void*)y_kernel<T, NT, 1, true, S>,
                               (const void*)y_kernel<T, NT, 2, true, S>},
                              {(const void*)y_kernel<T, NT, 0, true, S, big>,
@@ -1961,22 +1967,22 @@ bool y_threads_supported(int is_f64, int nt) {
     return nt == 1024 && !is_f64;
 }
 
-template <typename T, bool FULL, bool BIG>
+template <typename T, bool FULL, bool LTW>
 static hipError_t launch_y_full(int stage, int s64, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
                                 int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                                 const void* twst, int step, hipStream_t s) {
     switch (nt) {
     case 256:
-        if constexpr (!BIG)
-            return launch_y_nt<T, 256, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+        if constexpr (!(FULL && LTW))
+            return launch_y_nt<T, 256, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
                                                   tabs, twst, step, s);
         return hipErrorInvalidValue;
     case 512:
-        return launch_y_nt<T, 512, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+        return launch_y_nt<T, 512, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
                                               twst, step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024, FULL, BIG>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+            return launch_y_nt<T, 1024, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
                                                    tabs, twst, step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
@@ -1993,8 +1999,8 @@ hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc
                                             tabs, twst, step, s);
     return full ? launch_y_full<T, true, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
                                                 tabs, twst, step, s)
-                : launch_y_full<T, false, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P,
-                                                 U, tabs, twst, step, s);
+                : launch_y_full<T, false, sizeof(T) == 4>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B,
+                                                          By, P, U, tabs, twst, step, s);
 }
 
 // b^ = sigma F^ in place on one instance's tiled tau-spectrum (element e of
@@ -2102,7 +2108,7 @@ hipError_t launch_tau_adj(int stage, const InstDesc* d_desc, const TauItem* d_it
     }
 }
 
-template <typename T, int NT, bool BIG>
+template <typename T, int NT, bool LTW>
 static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, const void* In,
                                   void* Lh, void* Tout, void* Rout, const void* tabs, const void* twst, hipStream_t s) {
     dim3 g(n_items), b(NT);
@@ -2113,9 +2119,9 @@ static hipError_t launch_y_adj_nt(int stage, const InstDesc* d_desc, const YItem
     const cpx<T>* tb = static_cast<const cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 1)
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1, BIG>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 1, LTW>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     else
-        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2, BIG>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
+        hipLaunchKernelGGL((y_adj_kernel<T, NT, 2, LTW>), g, b, 0, s, d_desc, d_items, in, lh, to, ro, tb, ws);
     return hipGetLastError();
 }
 
