@@ -62,26 +62,29 @@ template <typename T> __device__ __forceinline__ T nmax(T a, T b) { return __bui
 // Raw buffer access (gfx9 descriptor: 32-bit data format, no stride, no
 // range limit below 2 GiB): a per-thread byte offset plus a wave-uniform byte
 // offset, so that accesses at uniform strides need no per-access address
-// arithmetic.  Every caller stays inside the array it addresses.
+// arithmetic.  Every caller stays inside the array it addresses.  CP is the
+// access's cache policy: 0, or CP_NT (the gfx950 non-temporal bit: the lines
+// are not kept for reuse in L2 and the Infinity Cache).
+constexpr int CP_NT = 2;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
 }
-template <typename T>
+template <typename T, int CP = 0>
 __device__ __forceinline__ cpx<T> buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
     } else {
-        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, CP));
     }
 }
-template <typename T>
+template <typename T, int CP = 0>
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, cpx<T> v) {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
     if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, CP);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff, CP);
     }
 }
 template <typename T> __device__ __forceinline__ bool finite_val(T x);
@@ -1019,6 +1022,13 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // W row runs of one half-wave (R rows of 8 bytes each) then cover the banks
 // once instead of W/2 times (2-way conflicts at W = 4 with R = 64/W).
 //
+// Cache policy (full tiles): every store of a tile (P, U, C~, the h Phi2
+// table) is non-temporal.  Each is read back only by a later kernel, after
+// at least one more 128 MB-class array has streamed through, so keeping the
+// written lines in L2 and the Infinity Cache only evicts lines the block is
+// still reading.  With an FP64 state the loads of U, P and the tables are
+// non-temporal as well (read once per step); in FP32 that measured slower.
+//
 // S: precision of the spectral state U and the stage value P (T, or double
 // in FP32 plans that keep their state in FP64: the combine then runs in FP64
 // with the step's multipliers evaluated in FP64, and only the inputs of the
@@ -1041,6 +1051,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // byte offsets of tile elements in the state arrays are ES times those in the others
     constexpr unsigned ES = sizeof(cpx<S>) / sizeof(cpx<T>);
     constexpr bool S64 = !std::is_same<S, T>::value;
+    // full tiles: loads of U, P and the tables non-temporal with an FP64 state
+    constexpr int CPL = sizeof(S) == 8 ? CP_NT : 0;
     const int tid = threadIdx.x;
     // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...
     const cpx<T>* src = STAGE == 0 ? C : B;
@@ -1170,13 +1182,13 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             // one item at a time (the FP64 multiplier code needs the registers);
             // the U loads of the next item are in flight during this item's
             // multipliers.  Column 0 of the first tile is handled pointwise below.
-            cpx<S> u0 = buf_ld<S>(rU, ES * v0, 0), u1 = buf_ld<S>(rU, ES * vm0, 0);
+            cpx<S> u0 = buf_ld<S, CPL>(rU, ES * v0, 0), u1 = buf_ld<S, CPL>(rU, ES * vm0, 0);
             #pragma unroll
             for (int q = 0; q < QH; ++q) {
                 cpx<S> x0 = u0, x1 = u1;
                 if (q + 1 < QH) {
-                    x0 = buf_ld<S>(rU, ES * vself(q + 1), ES * (q + 1) * NT * E);
-                    if (q + 1 < 8) x1 = buf_ld<S>(rU, ES * vpart(q + 1), ES * spart(q + 1));
+                    x0 = buf_ld<S, CPL>(rU, ES * vself(q + 1), ES * (q + 1) * NT * E);
+                    if (q + 1 < 8) x1 = buf_ld<S, CPL>(rU, ES * vpart(q + 1), ES * spart(q + 1));
                 }
                 if (q < 8 || first) {
                     const int n = j0 + q * dq;
@@ -1189,19 +1201,19 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                         nyquist_multipliers<S>(d, e, p1, p2);
                         P2 = cpx<S>{p2, (S)0};
                     }
-                    buf_st<T>(rP2, vself(q), q * NT * E, cvs<T>(P2));
+                    buf_st<T, CP_NT>(rP2, vself(q), q * NT * E, cvs<T>(P2));
                     {
                         const int li = s0 + q * sq;
                         const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                         const cpx<S> EU = cmul(E0, u0);
-                        if (keep_c) buf_st<S>(rP, ES * vself(q), ES * q * NT * E, EU + cmul(P1 - P2, bh));
+                        if (keep_c) buf_st<S, CP_NT>(rP, ES * vself(q), ES * q * NT * E, EU + cmul(P1 - P2, bh));
                         lds[li] = cvs<T>(EU + cmul(P1, bh));
                     }
                     if (two) {
                         const int li = s1 - q * sq;
                         const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                         const cpx<S> EU = cmul(E0, u1);
-                        if (keep_c) buf_st<S>(rP, ES * vpart(q), ES * spart(q), EU + cmul(P1 - P2, bh));
+                        if (keep_c) buf_st<S, CP_NT>(rP, ES * vpart(q), ES * spart(q), EU + cmul(P1 - P2, bh));
                         lds[li] = cvs<T>(EU + cmul(P1, bh));
                     }
                 }
@@ -1222,15 +1234,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     const int qq = q0 + q;
                     const unsigned vs = vself(qq), ss = qq * NT * E;
                     if (STAGE == 1) {
-                        tb[q][0] = buf_ld<T>(rE, vs, ss);
-                        tb[q][1] = buf_ld<T>(rP1, vs, ss);
-                        tb[q][2] = buf_ld<T>(rP2, vs, ss);
-                        ua[q][0] = buf_ld<S>(rU, ES * vs, ES * ss);
-                        ua[q][1] = qq < 8 ? buf_ld<S>(rU, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
+                        tb[q][0] = buf_ld<T, CPL>(rE, vs, ss);
+                        tb[q][1] = buf_ld<T, CPL>(rP1, vs, ss);
+                        tb[q][2] = buf_ld<T, CPL>(rP2, vs, ss);
+                        ua[q][0] = buf_ld<S, CPL>(rU, ES * vs, ES * ss);
+                        ua[q][1] = qq < 8 ? buf_ld<S, CPL>(rU, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
                     } else {
-                        tb[q][2] = buf_ld<T>(rP2, vs, ss);
-                        ua[q][0] = buf_ld<S>(rP, ES * vs, ES * ss);
-                        ua[q][1] = qq < 8 ? buf_ld<S>(rP, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
+                        tb[q][2] = buf_ld<T, CPL>(rP2, vs, ss);
+                        ua[q][0] = buf_ld<S, CPL>(rP, ES * vs, ES * ss);
+                        ua[q][1] = qq < 8 ? buf_ld<S, CPL>(rP, ES * vpart(qq), ES * spart(qq)) : ua[q][0];
                     }
                 }
                 #pragma unroll
@@ -1247,11 +1259,11 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                         const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                         if (STAGE == 1) {
                             const cpx<S> EU = cmul(cvs<S>(tb[q][0]), ua[q][pass]);
-                            if (keep_c) buf_st<S>(rP, ES * vv, ES * ss, EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh));
+                            if (keep_c) buf_st<S, CP_NT>(rP, ES * vv, ES * ss, EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh));
                             lds[li] = cvs<T>(EU + cmul(cvs<S>(tb[q][1]), bh));
                         } else {
                             const cpx<S> un = ua[q][pass] + cmul(cvs<S>(tb[q][2]), bh);
-                            if (keep_c) buf_st<S>(rU, ES * vv, ES * ss, (S)Ny * un);
+                            if (keep_c) buf_st<S, CP_NT>(rU, ES * vv, ES * ss, (S)Ny * un);
                             lds[li] = cvs<T>(un);
                         }
                     }
@@ -1373,7 +1385,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
         asm volatile("" : "+v"(sb));
         if (keep_c) {
             #pragma unroll
-            for (int q = 0; q < 16; ++q) buf_st<T>(rc, tid * E, q * NT * E, lds[sb + q * sq]);
+            for (int q = 0; q < 16; ++q) buf_st<T, CP_NT>(rc, tid * E, q * NT * E, lds[sb + q * sq]);
         }
     } else {
         tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
