@@ -53,6 +53,7 @@ struct kzk_plan {
     int tau_prog = 0;                     // every instance has M/16 >= W and M >= 256 (tau-pass pair indexing)
     int gk = 0;                           // > 0: every instance has M = 7 * 2^gk (mixed-radix tau-pass)
     int y_full = 0;                       // every instance has W n_y = 16 y_threads and n_y >= 512 (full y tiles)
+    int y_ntl = 0;                        // FP64 state arrays above 64 MiB: non-temporal y-pass loads
     int max_ny = 0;                       // largest n_y of the plan (8192 needs full tiles of 512+ threads)
     bool any_D_sched = false;
     int scheme = 0;                       // 0: ExpRK22, 1: exponential Euler (every solve)
@@ -357,10 +358,10 @@ hipError_t ypass(kzk_plan* p, int stage, int step = 0) {
     ProfScope ps(p, stage == 1 ? KZK_KIND_Y1 : stage == 2 ? KZK_KIND_Y2 : KZK_KIND_TRANSFORM);
     const void* by = stage > 0 && p->transport ? p->dBys : nullptr;
     if (p->dtype == KZK_F32)
-        return kzk::launch_y<float>(stage, p->s64, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid,
-                                    p->dC, p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
-    return kzk::launch_y<double>(stage, 0, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid, p->dC,
-                                 p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+        return kzk::launch_y<float>(stage, p->s64, p->y_ntl, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items,
+                                    p->y_grid, p->dC, p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
+    return kzk::launch_y<double>(stage, 0, p->y_ntl, p->y_threads, p->y_full, p->dDesc, p->dY, p->n_y_items, p->y_grid,
+                                 p->dC, p->dB, by, p->dP, p->dU, p->dTab, p->dTwSt, step, p->stream);
 }
 
 // The mean tau-mode column of the solves with the regularised multiplier,
@@ -590,6 +591,15 @@ kzk_status create_plan(const kzk_params* params, int32_t n_inst, void* hip_strea
     p->u_off[n_inst] = uo;
     p->state_elems = so;
     p->tab_elems = to;
+    // FP64 spectral state (FP64 plans, or FP32 with state_fp64): above a
+    // quarter of the 256 MB Infinity Cache per array (a step streams about
+    // six such arrays) the y-passes load the state non-temporally; below
+    // it, where the arrays largely stay cached, cached loads are faster.
+    {
+        constexpr size_t NTL_MIN_BYTES = (size_t)64 << 20;
+        const bool s64state = p->dtype == KZK_F64 || p->s64;
+        p->y_ntl = s64state && p->state_elems * 16 > NTL_MIN_BYTES;
+    }
     for (int i = 0; i < n_inst; ++i) p->desc[i].tab_stride = (long long)to;
     // the tau-pass twiddle table: e^{-2 pi i k / 2^log2_ntw}, or with
     // n_tau = 7 * 2^(K+1) the table e^{-2 pi i k / n_tau} of that length

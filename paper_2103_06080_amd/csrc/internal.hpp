@@ -79,9 +79,11 @@ bool tau_threads_supported(int dtype_is_f64, int nt);
 // By: tau-spectrum of the transverse transport part of b (instances with
 // vel = 1; nullptr otherwise), added to sigma_m B before the y-transform.
 // s64: an FP32 plan whose spectral state U and stage value P are FP64.
+// ntl: full tiles with an FP64 state (FP64 plans, or s64) load U, P and the
+// tables non-temporally (for arrays larger than the caches).
 template <typename T>
-hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+hipError_t launch_y(int stage, int s64, int ntl, int nt, int full, const InstDesc* d_desc, const YItem* d_items,
+                    int n_items, int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                     const void* twst, int step, hipStream_t s);
 
 // Transverse part of b on the physical field u at node `node`:

@@ -87,6 +87,12 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, 
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff, CP);
     }
 }
+// Non-temporal store of one complex value (plain addressing).
+template <typename T>
+__device__ __forceinline__ void st_nt(cpx<T>* p, cpx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(__builtin_bit_cast(v2, v), reinterpret_cast<v2*>(p));
+}
 template <typename T> __device__ __forceinline__ bool finite_val(T x);
 template <> __device__ __forceinline__ bool finite_val<float>(float x) { return fabsf(x) <= FLT_MAX; }
 template <> __device__ __forceinline__ bool finite_val<double>(double x) { return fabs(x) <= DBL_MAX; }
@@ -978,13 +984,16 @@ __device__ __forceinline__ void tile_put(cpx<T>* lds, const T (&vr)[16], const T
 }
 
 // skips column 0 of the first tile (col0), whose modes are handled pointwise
-template <typename T, int NT>
+template <typename T, int NT, bool NTS = false>
 __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>* lds, int ne, int tid, int W, int lw,
                                            int Ny, bool col0) {
     #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = tid + q * NT;
-        if (e < ne && !(col0 && (e & (W - 1)) == 0)) g[e] = lds[tile_li(e, W, lw, Ny)];
+        if (e < ne && !(col0 && (e & (W - 1)) == 0)) {
+            if constexpr (NTS) st_nt(g + e, lds[tile_li(e, W, lw, Ny)]);
+            else g[e] = lds[tile_li(e, W, lw, Ny)];
+        }
     }
 }
 
@@ -1022,12 +1031,13 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // W row runs of one half-wave (R rows of 8 bytes each) then cover the banks
 // once instead of W/2 times (2-way conflicts at W = 4 with R = 64/W).
 //
-// Cache policy (full tiles): every store of a tile (P, U, C~, the h Phi2
-// table) is non-temporal.  Each is read back only by a later kernel, after
-// at least one more 128 MB-class array has streamed through, so keeping the
-// written lines in L2 and the Infinity Cache only evicts lines the block is
-// still reading.  With an FP64 state the loads of U, P and the tables are
-// non-temporal as well (read once per step); in FP32 that measured slower.
+// Cache policy: every store of a tile (P, U, C~, the h Phi2 table) is
+// non-temporal: each is read back only by a later kernel, after other
+// arrays have streamed through, so keeping the written lines in L2 and the
+// Infinity Cache mostly evicts lines the blocks are still reading.  NTL (full
+// tiles with an FP64 state whose arrays outgrow the caches): the loads of U,
+// P and the tables, read once per step, are non-temporal as well.  In FP32,
+// and on arrays the 256 MB Infinity Cache holds, cached loads measured faster.
 //
 // S: precision of the spectral state U and the stage value P (T, or double
 // in FP32 plans that keep their state in FP64: the combine then runs in FP64
@@ -1041,7 +1051,7 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // by the FP32 general-tile blocks, whose element indexing leaves no room for
 // held twiddles under the 128-VGPR cap (they would spill about 120 VGPRs to
 // scratch; the loaded form needs none and gives bit-identical results).
-template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool LTW = false>
+template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool LTW = false, bool NTL = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
         const cpx<T>* __restrict__ B, const cpx<T>* __restrict__ By, cpx<S>* __restrict__ P, cpx<S>* __restrict__ U,
@@ -1051,8 +1061,8 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
     // byte offsets of tile elements in the state arrays are ES times those in the others
     constexpr unsigned ES = sizeof(cpx<S>) / sizeof(cpx<T>);
     constexpr bool S64 = !std::is_same<S, T>::value;
-    // full tiles: loads of U, P and the tables non-temporal with an FP64 state
-    constexpr int CPL = sizeof(S) == 8 ? CP_NT : 0;
+    // full tiles: loads of U, P and the tables (NTL)
+    constexpr int CPL = NTL ? CP_NT : 0;
     const int tid = threadIdx.x;
     // Persistent blocks: block b takes the tiles b, b + gridDim.x, ...
     const cpx<T>* src = STAGE == 0 ? C : B;
@@ -1307,7 +1317,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     nyquist_multipliers<S>(d, e, p1, p2);
                     P2 = cpx<S>{p2, (S)0};
                 }
-                tP2[h] = cvs<T>(P2);
+                st_nt(tP2 + h, cvs<T>(P2));
                 #pragma unroll
                 for (int pass = 0; pass < 2; ++pass) {
                     if (pass == 1 && !two) break;
@@ -1315,7 +1325,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                     const int e = j * W + cc, li = padi(cc * Ny + j);
                     const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                     const cpx<S> EU = cmul(E, pass ? u1 : u0);
-                    if (keep_col) Pt[e] = EU + cmul(P1 - P2, bh);
+                    if (keep_col) st_nt(Pt + e, EU + cmul(P1 - P2, bh));
                     lds[li] = cvs<T>(EU + cmul(P1, bh));
                 }
             }
@@ -1360,13 +1370,13 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
                 const cpx<S> bh = cvs<S>(cmul(sg, lds[li]));
                 if (STAGE == 1) {
                     const cpx<S> EU = cmul(cvs<S>(tb[q][0]), ua[q][pass]);
-                    if (keep_col) Pt[e] = EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh);
+                    if (keep_col) st_nt(Pt + e, EU + cmul(cvs<S>(tb[q][1] - tb[q][2]), bh));
                     lds[li] = cvs<T>(EU + cmul(cvs<S>(tb[q][1]), bh));
                 } else {
                     // un = U^{n+1} / n_y (the tables carry the 1/n_y of the inverse y-FFT);
                     // the state keeps the unnormalised spectrum (a power-of-two scaling, exact)
                     const cpx<S> un = ua[q][pass] + cmul(cvs<S>(tb[q][2]), bh);
-                    if (keep_col) Ut[e] = (S)Ny * un;
+                    if (keep_col) st_nt(Ut + e, (S)Ny * un);
                     lds[li] = cvs<T>(un);
                 }
             }
@@ -1388,7 +1398,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_k
             for (int q = 0; q < 16; ++q) buf_st<T, CP_NT>(rc, tid * E, q * NT * E, lds[sb + q * sq]);
         }
     } else {
-        tile_store<T, NT>(Ct, lds, ne, tid, W, lw, Ny, col0);
+        tile_store<T, NT, true>(Ct, lds, ne, tid, W, lw, Ny, col0);
     }
 #undef KZK_LI
     if (col0) {
@@ -1892,10 +1902,15 @@ hipError_t launch_tau(int mode, int nt, const InstDesc* d_desc, const TauItem* d
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NT, bool FULL, typename S, bool LTW>
-static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d_items, int n_items, int max_blocks,
-                               void* C, const void* B, const void* By, void* P, void* U, void* tabs, const void* twst,
-                               int step, hipStream_t s) {
+template <typename T, int NT, bool FULL, typename S, bool LTW, bool NTL = false>
+static hipError_t launch_y_nts(int stage, int ntl, const InstDesc* d_desc, const YItem* d_items, int n_items,
+                               int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+                               const void* twst, int step, hipStream_t s) {
+    if constexpr (FULL && sizeof(S) == 8 && !NTL) {
+        if (ntl)
+            return launch_y_nts<T, NT, FULL, S, LTW, true>(stage, ntl, d_desc, d_items, n_items, max_blocks, C, B, By,
+                                                           P, U, tabs, twst, step, s);
+    }
     dim3 g(max_blocks > 0 && max_blocks < n_items ? max_blocks : n_items), b(NT);
     cpx<T>* c = static_cast<cpx<T>*>(C);
     const cpx<T>* bb = static_cast<const cpx<T>*>(B);
@@ -1905,29 +1920,29 @@ static hipError_t launch_y_nts(int stage, const InstDesc* d_desc, const YItem* d
     cpx<T>* tb = static_cast<cpx<T>*>(tabs);
     const cpx<T>* ws = static_cast<const cpx<T>*>(twst);
     if (stage == 0)
-        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 0, FULL, S, LTW, NTL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else if (stage == 1)
-        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 1, FULL, S, LTW, NTL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     else
-        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S, LTW>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
+        hipLaunchKernelGGL((y_kernel<T, NT, 2, FULL, S, LTW, NTL>), g, b, 0, s, d_desc, d_items, n_items, c, bb, by, p, u, tb,
                            ws, step);
     return hipGetLastError();
 }
 
 // s64: FP32 plan with the state in FP64
 template <typename T, int NT, bool FULL, bool LTW>
-static hipError_t launch_y_nt(int stage, int s64, const InstDesc* d_desc, const YItem* d_items, int n_items,
+static hipError_t launch_y_nt(int stage, int s64, int ntl, const InstDesc* d_desc, const YItem* d_items, int n_items,
                               int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                               const void* twst, int step, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         if (s64)
-            return launch_y_nts<T, NT, FULL, double, LTW>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P,
-                                                          U, tabs, twst, step, s);
+            return launch_y_nts<T, NT, FULL, double, LTW>(stage, ntl, d_desc, d_items, n_items, max_blocks, C, B, By,
+                                                          P, U, tabs, twst, step, s);
     }
-    return launch_y_nts<T, NT, FULL, T, LTW>(stage, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs, twst,
-                                             step, s);
+    return launch_y_nts<T, NT, FULL, T, LTW>(stage, ntl, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
+                                             twst, step, s);
 }
 
 // full: 0 general tiles, 1 full tiles, 2 full tiles with an 8192-row instance
@@ -1980,39 +1995,39 @@ bool y_threads_supported(int is_f64, int nt) {
 }
 
 template <typename T, bool FULL, bool LTW>
-static hipError_t launch_y_full(int stage, int s64, int nt, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                                int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
-                                const void* twst, int step, hipStream_t s) {
+static hipError_t launch_y_full(int stage, int s64, int ntl, int nt, const InstDesc* d_desc, const YItem* d_items,
+                                int n_items, int max_blocks, void* C, const void* B, const void* By, void* P, void* U,
+                                void* tabs, const void* twst, int step, hipStream_t s) {
     switch (nt) {
     case 256:
         if constexpr (!(FULL && LTW))
-            return launch_y_nt<T, 256, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
-                                                  tabs, twst, step, s);
+            return launch_y_nt<T, 256, FULL, LTW>(stage, s64, ntl, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+                                                  U, tabs, twst, step, s);
         return hipErrorInvalidValue;
     case 512:
-        return launch_y_nt<T, 512, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U, tabs,
-                                              twst, step, s);
+        return launch_y_nt<T, 512, FULL, LTW>(stage, s64, ntl, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
+                                              tabs, twst, step, s);
     case 1024:
         if constexpr (sizeof(T) == 4)
-            return launch_y_nt<T, 1024, FULL, LTW>(stage, s64, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
-                                                   tabs, twst, step, s);
+            return launch_y_nt<T, 1024, FULL, LTW>(stage, s64, ntl, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+                                                   U, tabs, twst, step, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_y(int stage, int s64, int nt, int full, const InstDesc* d_desc, const YItem* d_items, int n_items,
-                    int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
+hipError_t launch_y(int stage, int s64, int ntl, int nt, int full, const InstDesc* d_desc, const YItem* d_items,
+                    int n_items, int max_blocks, void* C, const void* B, const void* By, void* P, void* U, void* tabs,
                     const void* twst, int step, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (full == 2)
-        return launch_y_full<T, true, true>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
-                                            tabs, twst, step, s);
-    return full ? launch_y_full<T, true, false>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P, U,
-                                                tabs, twst, step, s)
-                : launch_y_full<T, false, sizeof(T) == 4>(stage, s64, nt, d_desc, d_items, n_items, max_blocks, C, B,
-                                                          By, P, U, tabs, twst, step, s);
+        return launch_y_full<T, true, true>(stage, s64, ntl, nt, d_desc, d_items, n_items, max_blocks, C, B, By, P,
+                                            U, tabs, twst, step, s);
+    return full ? launch_y_full<T, true, false>(stage, s64, ntl, nt, d_desc, d_items, n_items, max_blocks, C, B, By,
+                                                P, U, tabs, twst, step, s)
+                : launch_y_full<T, false, sizeof(T) == 4>(stage, s64, ntl, nt, d_desc, d_items, n_items, max_blocks,
+                                                          C, B, By, P, U, tabs, twst, step, s);
 }
 
 // b^ = sigma F^ in place on one instance's tiled tau-spectrum (element e of
@@ -2192,7 +2207,7 @@ void stage_twiddles(double* out) {
     template hipError_t launch_tau<T>(int, int, const InstDesc*, const TauItem*, int, const T*, T*, const void*,    \
                                       void*, const void*, const void*, int, int, int, int, int, int, unsigned*,     \
                                       hipStream_t);                                                                 \
-    template hipError_t launch_y<T>(int, int, int, int, const InstDesc*, const YItem*, int, int, void*,             \
+    template hipError_t launch_y<T>(int, int, int, int, int, const InstDesc*, const YItem*, int, int, void*,        \
                                     const void*, const void*, void*, void*, void*, const void*, int, hipStream_t);   \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, void*, int, hipStream_t);                   \
     template hipError_t launch_flux_diff<T>(const InstDesc*, int, long long, void*, const void*, hipStream_t);       \
