@@ -161,7 +161,10 @@ size_t kzk_inst_offset(const kzk_plan *plan, int32_t i);
 kzk_status kzk_set_stream(kzk_plan *plan, void *hip_stream);
 
 /* Enable (1) or disable (0) replay of kzk_step through a captured HIP graph.
- * The graph for one (u_dev, first_step, n_steps) is cached and reused. */
+ * The graph for one (u_dev, first_step, n_steps) is cached and reused.  The
+ * legacy default stream cannot be captured: with graphs enabled, kzk_step on
+ * a plan without a stream of its own (hip_stream NULL at kzk_create or
+ * kzk_set_stream) returns KZK_ERR_STATE. */
 kzk_status kzk_set_graph(kzk_plan *plan, int32_t enable);
 
 /* Select the y-pass block size (256, 512 or 1024 threads; 1024 in FP32

@@ -176,7 +176,12 @@ def step_noalloc(problems, u, first: int = 0, n_steps: int = 1, dtype: str = "f6
 
 
 class Plan:
-    """A kzk_plan for one or several solves (uneven grids allowed)."""
+    """A kzk_plan for one or several solves (uneven grids allowed).
+
+    stream: the torch stream the plan enqueues on (default: the current
+    stream).  graph=True replays marches as HIP graphs, which needs a stream
+    other than the legacy default stream (kzk_step raises KZK_ERR_STATE
+    there)."""
 
     def __init__(self, problems, dtype: str = "f64", stream=None, cfl_max: float = 1.0,
                  y_threads: Optional[int] = None, graph: bool = False, tau_threads: Optional[int] = None,
