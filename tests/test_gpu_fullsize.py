@@ -170,6 +170,27 @@ def test_graph_replays_match_eager(torch_cuda):
         stream.synchronize()
 
 
+def test_graph_replay_needs_a_stream_of_its_own(torch_cuda):
+    """The legacy default stream cannot be captured: with graphs on, a plan
+    without a stream of its own rejects kzk_step (KZK_ERR_STATE) before
+    enqueueing anything, and marches eagerly again once graphs are off."""
+    from paper_2103_06080_amd import kzk
+    p = I.c1(n_steps=5)
+    plan = kzk.Plan(p, dtype="f64", stream=torch_cuda.cuda.default_stream(), graph=True)
+    u = plan.pack([p.u0])
+    before = u.clone()
+    with pytest.raises(kzk.KZKError) as e:
+        plan.step(u, 0, 5)
+    assert e.value.code == 7
+    assert plan.poll() == 0
+    assert torch_cuda.equal(u, before)
+    plan.set_graph(False)
+    plan.step(u, 0, 5)
+    assert plan.poll() == 0
+    assert not torch_cuda.equal(u, before)
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_autotune_picks_a_supported_size_and_keeps_results(torch_cuda, orc, dtype):
     from paper_2103_06080_amd import kzk
