@@ -1031,8 +1031,8 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // W row runs of one half-wave (R rows of 8 bytes each) then cover the banks
 // once instead of W/2 times (2-way conflicts at W = 4 with R = 64/W).
 //
-// Cache policy: every store of a tile (P, U, C~, the h Phi2 table) is
-// non-temporal: each is read back only by a later kernel, after other
+// Cache policy: every store of stages 1 and 2 (P, U, C~, the h Phi2 table)
+// is non-temporal: each is read back only by a later kernel, after other
 // arrays have streamed through, so keeping the written lines in L2 and the
 // Infinity Cache mostly evicts lines the blocks are still reading.  NTL (full
 // tiles with an FP64 state whose arrays outgrow the caches): the loads of U,
@@ -1050,7 +1050,7 @@ __device__ __forceinline__ void tile_store(cpx<T>* __restrict__ g, const cpx<T>*
 // stages with twiddles, more than the registers hold beside the tile), and
 // by the FP32 general-tile blocks, whose element indexing leaves no room for
 // held twiddles under the 128-VGPR cap (they would spill about 120 VGPRs to
-// scratch; the loaded form needs none and gives bit-identical results).
+// scratch; the loaded form spills 2 and gives bit-identical results).
 template <typename T, int NT, int STAGE, bool FULL, typename S = T, bool LTW = false, bool NTL = false>
 __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 4 : 1) void y_kernel(
         const InstDesc* __restrict__ descs, const YItem* __restrict__ items, int n_items, cpx<T>* __restrict__ C,
