@@ -110,17 +110,19 @@ def test_transport_march_matches_oracle(torch_cuda, orc, dtype, case):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("pow2", [False, True])
-def test_paper_set1_matches_oracle(torch_cuda, orc, dtype, pow2):
+@pytest.mark.parametrize("k,n_steps,pow2", [(1, 6, False), (1, 6, True), (2, 3, False), (2, 3, True),
+                                            (3, 3, False), (3, 3, True), (4, 2, False)])
+def test_paper_set_matches_oracle(torch_cuda, orc, dtype, k, n_steps, pow2):
     """The paper's workload (Sec. 4 parameters, random medium, regularised
-    multiplier, its N-wave) on set 1's grid (448 x 1024: N_theta = 448 and the
-    power of two nearest N_rho = 1250) and on the 512 x 1024 power-of-two
-    grid, first steps (h = 0.4)."""
-    p = I.paper_set(1, reg_eps=EPS[dtype], n_steps=6, pow2=pow2)
+    multiplier, its N-wave) on the grids of sets 1-4 of Table 0 (N_theta =
+    448 ... 3584 tau-points and the power of two nearest N_rho rows: 448 x
+    1024, 896 x 2048, 1792 x 4096, 3584 x 8192) and on the power-of-two grids
+    nearest sets 1-3, first steps."""
+    p = I.paper_set(k, reg_eps=EPS[dtype], n_steps=n_steps, pow2=pow2)
     ref = orc.run(p)
     got = march(p, dtype)
     e2, em = rel_l2(got, ref), max_rel(got, ref)
-    print("paper set 1 %dx%d %s, 6 steps: rel l2 %.2e max %.2e" % (p.n_tau, p.n_y, dtype, e2, em))
+    print("paper set %d %dx%d %s, %d steps: rel l2 %.2e max %.2e" % (k, p.n_tau, p.n_y, dtype, n_steps, e2, em))
     assert e2 < TOL[dtype] and em < TOL[dtype], (e2, em)
 
 
