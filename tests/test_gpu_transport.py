@@ -144,19 +144,20 @@ def test_transport_march_stays_within_the_tabulated_nodes(torch_cuda):
 
 
 @pytest.mark.parametrize("dtype,bar", [("f64", 1e-12), ("f32", 1e-4)])
-def test_paper_set1_whole_march_matches_stored_oracle_rows(torch_cuda, dtype, bar):
-    """The paper's workload on set 1's grid (448 x 1024) over its whole march
-    (300 steps of h = 0.4 to Sigma = 120, Sec. 4), in two halves, against the
-    FP64 oracle's march stored on 16 rows at steps 150 and 300
-    (tests/golden/paper_set1_oracle_rows.npz, written by
-    tests/golden/make_paper_set1_reference.py, which calls only the oracle;
+@pytest.mark.parametrize("k", [1, 2])
+def test_paper_set_whole_march_matches_stored_oracle_rows(torch_cuda, dtype, bar, k):
+    """The paper's workload on the grid of set k (448 x 1024, 896 x 2048) over
+    its whole march (N_sigma steps to Sigma = 120, Sec. 4), in two halves,
+    against the FP64 oracle's march stored on 16 rows at the middle and the
+    end (tests/golden/paper_set<k>_oracle_rows.npz, written by
+    tests/golden/make_paper_set_reference.py, which calls only the oracle;
     regularisation with the machine epsilon of the working precision)."""
     import os
     from paper_2103_06080_amd import kzk
-    path = os.path.join(os.path.dirname(__file__), "golden", "paper_set1_oracle_rows.npz")
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_set%d_oracle_rows.npz" % k)
     ref = np.load(path)
     rows = ref["rows"]
-    p = I.paper_set(1, reg_eps=EPS[dtype])
+    p = I.paper_set(k, reg_eps=EPS[dtype])
     half = p.n_steps // 2
     plan = kzk.Plan(p, dtype=dtype)
     u = plan.pack([p.u0])
@@ -168,5 +169,5 @@ def test_paper_set1_whole_march_matches_stored_oracle_rows(torch_cuda, dtype, ba
         want = ref["%s_step%d" % (dtype, first + n)]
         errs.append((rel_l2(got, want), max_rel(got, want)))
     plan.close()
-    print("paper set 1 whole march %s: rel l2 / max at steps %d, %d: %s" % (dtype, half, p.n_steps, errs))
+    print("paper set %d whole march %s: rel l2 / max at steps %d, %d: %s" % (k, dtype, half, p.n_steps, errs))
     assert all(e2 < bar and em < bar for e2, em in errs), errs
