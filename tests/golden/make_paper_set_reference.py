@@ -10,7 +10,7 @@ eps = 2^-24 (the FP32 reference).
 Only the oracle (oracle/) and the seeded input generator are called.  Set 1
 takes a few minutes on a few CPU cores, set 2 about a quarter of an hour:
 
-    python tests/golden/make_paper_set_reference.py 1
+    python tests/golden/make_paper_set_reference.py 1 [f64,f32]
 """
 import os
 import sys
@@ -28,14 +28,14 @@ from paper_2103_06080_amd import inputs as I  # noqa: E402
 EPS = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
 
 
-def main(k):
+def main(k, tags):
     out_path = os.path.join(HERE, "paper_set%d_oracle_rows.npz" % k)
     n_y = I.PAPER_SET_GRIDS[k][1]
     rows = np.arange(0, n_y, n_y // 16)
     out = {"rows": rows}
     t0 = time.time()
-    for tag, eps in EPS.items():
-        p = I.paper_set(k, reg_eps=eps)
+    for tag in tags:
+        p = I.paper_set(k, reg_eps=EPS[tag])
         half = p.n_steps // 2
         u = oracle.run(p, n_steps=half, first=0, u=p.u0.copy())
         out["%s_step%d" % (tag, half)] = u[rows].copy()
@@ -43,9 +43,9 @@ def main(k):
         out["%s_step%d" % (tag, p.n_steps)] = u[rows].copy()
         out["%s_norm_step%d" % (tag, p.n_steps)] = np.array(np.linalg.norm(u))
         print("%s done after %.0f s" % (tag, time.time() - t0), flush=True)
-    np.savez(out_path, **out)
-    print("wrote", out_path, flush=True)
+        np.savez(out_path, **out)
+        print("wrote", out_path, flush=True)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, sys.argv[2].split(",") if len(sys.argv) > 2 else list(EPS))
