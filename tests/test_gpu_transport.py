@@ -144,12 +144,12 @@ def test_transport_march_stays_within_the_tabulated_nodes(torch_cuda):
 
 
 @pytest.mark.parametrize("dtype,bar", [("f64", 1e-12), ("f32", 1e-4)])
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_paper_set_whole_march_matches_stored_oracle_rows(torch_cuda, dtype, bar, k):
-    """The paper's workload on the grid of set k (448 x 1024, 896 x 2048) over
-    its whole march (N_sigma steps to Sigma = 120, Sec. 4), in two halves,
-    against the FP64 oracle's march stored on 16 rows at the middle and the
-    end (tests/golden/paper_set<k>_oracle_rows.npz, written by
+    """The paper's workload on the grid of set k (448 x 1024, 896 x 2048,
+    1792 x 4096) over its whole march (N_sigma steps to Sigma = 120, Sec. 4),
+    in two halves, against the FP64 oracle's march stored on 16 rows at the
+    middle and the end (tests/golden/paper_set<k>_oracle_rows.npz, written by
     tests/golden/make_paper_set_reference.py, which calls only the oracle;
     regularisation with the machine epsilon of the working precision)."""
     import os
